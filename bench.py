@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the msMINRES-CIQ hot path on one MI355X.
+
+One step = one full ciq_sqrt_mvm call on the Matern-5/2 workload (N = 50,000
+points in [0,1]^6, lengthscale 0.3, outputscale 1, noise 1e-3, S = 64 Gaussian
+right-hand sides, Q = 15, tol 1e-4): Lanczos eigenvalue bounds, HHT shifts,
+msMINRES to tolerance, weighted combine and the final product with K.
+Inputs are resident in device memory before the timed region.
+
+Prints ONE JSON line (metric, value, roofline, cpu_baseline, ...).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(p, iters: int, q: int, sample_rows: int = 4096) -> dict:
+    """The oracle, as written, on a bounded sample of the same workload:
+    rows [0, sample_rows) of K B (its blocked kernel product) plus two
+    full-size msMINRES vector steps (with a trivial operator), extrapolated to
+    one full solve of `iters` iterations + the final product."""
+    from oracle import kernels as okern
+    from oracle import msminres as oms
+
+    x = p.x.astype(np.float64)
+    b = p.b.astype(np.float64)
+    n, s = b.shape
+    t0 = time.perf_counter()
+    rows = np.arange(sample_rows)
+    for r0 in range(0, sample_rows, 256):
+        kr = okern.kernel_rows(p.kernel, x, p.lengthscale, p.outputscale, p.noise, rows[r0:r0 + 256])
+        _ = kr @ b
+    t_rows = time.perf_counter() - t0
+    t_mvm = t_rows * n / sample_rows
+    shifts = np.geomspace(1e-3, 1e3, q)
+    t1 = time.perf_counter()
+    oms.msminres(lambda v: v * 1.5, b, shifts, 2, 0.0)
+    t_vec = (time.perf_counter() - t1) / 2.0
+    t_solve = iters * (t_mvm + t_vec) + t_mvm
+    return {
+        "value": s / t_solve,
+        "unit": "columns/s",
+        "cores": len(os.sched_getaffinity(0)),
+        "kind": "oracle",
+        "sample": (f"oracle kernel product on rows 0..{sample_rows} of {n} ({t_rows:.1f}s) and 2 full-size "
+                   f"msMINRES vector steps ({2 * t_vec:.1f}s), extrapolated to {iters} iterations + 1 product "
+                   f"(est. {t_solve:.0f}s per solve of {s} columns)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--n", type=int, default=None, help="shrink N (testing only)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import torch
+    import paper_2006_11267_amd as ciq
+    import workloads
+
+    wl = workloads.workload(2, n=args.n)
+    p = wl.problems[0]
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(p.x).to(dev)
+    b = torch.from_numpy(p.b).to(dev)
+    prob = ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise)
+    n, s = p.b.shape
+    q, tol = wl.q, wl.tol
+    torch.cuda.synchronize()
+
+    def step(profile=False):
+        return ciq.ciq_sqrt_mvm(prob, b, q=q, max_iter=args.max_iter, tol=tol, seed=4001, profile=profile)
+
+    for i in range(args.warmup):
+        out, info, _ = step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: iters={info['iters']} converged={info['converged']}")
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    infos = []
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(args.steps):
+        out, info, _ = step(profile=True)
+        infos.append(info)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    ms_step = ms_total / args.steps
+    info = infos[-1]
+    log(f"timed: {ms_step:.1f} ms/step, iters={info['iters']}, converged={info['converged']}, "
+        f"max_rel_residual={info['max_rel_residual']:.2e}")
+
+    # dominant kernel: the kernel product, timed live with HIP events inside the solves
+    mvm_ms = sum(i["mvm_ms"] for i in infos)
+    mvm_n = sum(i["mvm_timed"] for i in infos)
+    avg_ms = mvm_ms / max(mvm_n, 1)
+    flops = 2.0 * n * n * s                 # algorithmic tile x V contraction per launch
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+
+    res = {
+        "metric": METRIC,
+        "value": s / (ms_step * 1e-3),
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "kernel": "matern52", "n": n, "d": p.d, "s": s, "q": q, "tol": tol,
+            "max_iter": args.max_iter, "iters": info["iters"], "converged": info["converged"],
+            "max_rel_residual": info["max_rel_residual"], "lambda_min": info["lambda_min"],
+            "lambda_max": info["lambda_max"], "mvm_per_step": info["mvm_count"],
+        },
+        "roofline": {
+            "bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+            "kernel": "mvm_f32_kernel", "avg_ms": avg_ms, "launches": mvm_n,
+        },
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle sample) ...")
+        res["cpu_baseline"] = cpu_baseline(p, info["iters"], q)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

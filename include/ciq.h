@@ -1,0 +1,208 @@
+/*
+ * ciq.h -- C ABI of libciq: msMINRES-CIQ matrix square roots on MI355X (gfx950).
+ *
+ * Method: Pleiss, Jankowiak, Eriksson, Damle, Gardner, "Fast Matrix Square
+ * Roots with Applications to Gaussian Processes and Bayesian Optimization"
+ * (NeurIPS 2020). For a kernel matrix
+ *
+ *     K = o^2 k(X, X) + sigma^2 I,      k = RBF or Matern-5/2 (isotropic or ARD)
+ *
+ * the library computes K^{-1/2} B and K^{1/2} B through the rational
+ * approximation of Sec. 3 (K^{-1/2} ~= sum_q w_q (t_q I + K)^{-1}), the
+ * Hale-Higham-Trefethen shifts/weights of Appendix B (Alg. S2) and one
+ * multi-shift MINRES run (Appendix C, Alg. S4) whose Lanczos recurrence shares
+ * a single on-the-fly kernel product K V per iteration across all Q shifts.
+ * K is never stored: every product regenerates its entries from X.
+ *
+ * Conventions shared by every entry point:
+ *  - Status: every call returns CIQ_OK (0) or one of the CIQ_E* codes below;
+ *    ciq_strerror() names it. Arguments are validated before any device work:
+ *    on CIQ_EINVAL nothing has been launched and no output was written.
+ *  - Memory: X, B, V, Y, out, solves, G, dB are caller-owned DEVICE buffers,
+ *    row-major with the stated leading dimension (in elements). Inputs are not
+ *    modified. Lengthscales, t/w tables, info and gradient scalars are HOST
+ *    memory. The library keeps a grow-only scratch area per device (freed at
+ *    process exit); calls on one device are serialised by an internal lock.
+ *  - Streams: work is queued on `stream` (0 = the null stream). Solver calls
+ *    (eig_bounds, sqrt/invsqrt, backward, batched) poll convergence and return
+ *    only after their work on `stream` has completed; ciq_kernel_mvm returns
+ *    immediately (asynchronous on `stream`).
+ *  - Element types: dtype CIQ_F64 uses double for X, B, V, Y, out, solves, G
+ *    and dB; every other dtype uses float for them. Lanczos/Givens scalars,
+ *    reductions, shifts, weights and eigenvalue bounds are always double.
+ *  - Non-convergence is not an error: see ciq_info.converged.
+ */
+#ifndef CIQ_H
+#define CIQ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CIQ_OK        0
+#define CIQ_EINVAL    1   /* bad argument (null pointer, size <= 0, bad enum, ...) */
+#define CIQ_ENOMEM    2   /* device scratch allocation failed                        */
+#define CIQ_EHIP      3   /* a HIP runtime call failed                               */
+#define CIQ_ENOTSUP   4   /* valid request this build does not implement             */
+#define CIQ_ENUMERIC  5   /* NaN/Inf met in the Lanczos scalars                      */
+
+/* ---- enums --------------------------------------------------------------- */
+#define CIQ_KERNEL_RBF       0   /* k = exp(-r^2/2)                                  */
+#define CIQ_KERNEL_MATERN52  1   /* k = (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r)        */
+/* r^2 = sum_d (x_d - x'_d)^2 / l_d^2; l isotropic (1 value) or ARD (d values)      */
+
+#define CIQ_F64     0   /* double everywhere                                        */
+#define CIQ_F32     1   /* float vectors, float kernel tiles, FP32 MFMA contraction  */
+#define CIQ_BF16X3  2   /* float vectors; tile*V on bf16 MFMA with hi/lo split       */
+#define CIQ_F16X3   3   /* float vectors; tile*V on fp16 MFMA with hi/lo split       */
+
+#define CIQ_INVSQRT 0
+#define CIQ_SQRT    1
+
+#define CIQ_MAX_Q   64   /* quadrature points                                       */
+#define CIQ_MAX_D   16   /* input dimensions                                        */
+
+/* One kernel matrix K = outputscale * k(X, X) + noise * I. */
+typedef struct ciq_problem {
+    int32_t n;                 /* points (rows of X), >= 1                         */
+    int32_t d;                 /* input dimensions, 1..CIQ_MAX_D                   */
+    const void* x;             /* device, n x d row-major (ld = d), see dtype       */
+    int32_t kernel;            /* CIQ_KERNEL_*                                      */
+    int32_t n_lengthscale;     /* 1 (isotropic) or d (ARD)                          */
+    const double* lengthscale; /* host, n_lengthscale values > 0                    */
+    double outputscale;        /* o^2 > 0                                           */
+    double noise;              /* sigma^2 >= 0 (diagonal only)                      */
+} ciq_problem;
+
+/* Solver options. Zero-initialise and set what you need. */
+typedef struct ciq_opts {
+    int32_t dtype;             /* CIQ_F64 / CIQ_F32 / CIQ_BF16X3 / CIQ_F16X3        */
+    int32_t q;                 /* quadrature points Q, 1..CIQ_MAX_Q                 */
+    int32_t max_iter;          /* msMINRES iteration cap J (= products with K)      */
+    double tol;                /* stop shift q of column s when
+                                  |phibar|/||b_s|| <= tol (tol >= 0)                */
+    int32_t lanczos_steps;     /* Lanczos steps for the eigenvalue bounds (0 -> 20) */
+    uint64_t seed;             /* seed of the bounds' start vector (SplitMix64)     */
+    double lambda_min;         /* if lambda_min > 0 and lambda_max >= lambda_min:  */
+    double lambda_max;         /*   use these bounds, skip the Lanczos estimate     */
+    int32_t check_every;       /* iterations between host convergence polls (0: auto) */
+    int32_t profile;           /* 1: time every kernel-product launch of the msMINRES
+                                  loop with HIP events on `stream` (ciq_info.mvm_ms) */
+    int32_t reserved[6];
+} ciq_opts;
+
+/* Per-call report (host). Valid when the call returned CIQ_OK. */
+typedef struct ciq_info {
+    int32_t iters;             /* products with K in the msMINRES run               */
+    int32_t converged;         /* 1 if every (shift, column) met tol               */
+    int32_t q;                 /* quadrature points used                           */
+    int32_t mvm_count;         /* all products with K in the call (bounds included) */
+    double max_rel_residual;   /* max over (q, s) of |phibar|/||b_s||              */
+    double lambda_min;         /* bounds the quadrature was built on               */
+    double lambda_max;
+    double t[CIQ_MAX_Q];       /* shifts t_q (ascending)                           */
+    double w[CIQ_MAX_Q];       /* weights w_q                                      */
+    double mvm_ms;             /* opts.profile: summed device time of the timed
+                                  kernel-product launches (ms), else 0             */
+    int32_t mvm_timed;         /* number of launches in mvm_ms                     */
+    int32_t reserved;
+} ciq_info;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ciq_version(void);
+
+/* Name of a status code (static string, never NULL). */
+const char* ciq_strerror(int status);
+
+/*
+ * Hale-Higham-Trefethen quadrature for K^{-1/2} on [lambda_min, lambda_max]
+ * (Appendix B, nodes/weights formula with t_q = -sigma_q^2, w_q = -w~_q; Alg. S2
+ * with k'^2 = 1 - k^2). Host-only FP64; Jacobi sn/cn/dn by the AGM / descending
+ * Landen method and K' = pi / (2 AGM(1, k)) (Abramowitz & Stegun 16.4, 17.6),
+ * so 1 - k^2 is never formed.
+ *   t_out, w_out: caller-owned host arrays of length q; t ascending, all > 0; w > 0.
+ * Errors: CIQ_EINVAL unless 0 < lambda_min <= lambda_max < inf, 1 <= q <= CIQ_MAX_Q
+ * and both outputs are non-NULL.
+ */
+int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double* w_out);
+
+/*
+ * Y = K V for the s columns of V (the on-the-fly kernel product of Sec. 3.2 and
+ * Property 1; K is generated tile by tile and never stored).
+ *   v: device, n x s, leading dimension ldv >= s; y: device, n x s, ldy >= s.
+ *   dtype selects the element type and the contraction (see CIQ_F64..CIQ_F16X3).
+ * Asynchronous on `stream`. Errors: CIQ_EINVAL on bad sizes/pointers/enums.
+ */
+int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ldv,
+                   void* y, int ldy, hipStream_t stream);
+
+/*
+ * Extreme-eigenvalue estimate of K (Appendix B.2; Alg. S2 first step): `steps`
+ * Lanczos steps (0 -> 20) from v0 (device, n values; NULL -> a SplitMix64 draw
+ * from `seed`), eigenvalues of T by cyclic Jacobi on the host, widened as
+ *   lambda_max = theta_max + beta_{J+1} |y_J(theta_max)|   (Ritz residual),
+ *   lambda_min = min(theta_min, sigma^2) if sigma^2 > 0, else theta_min / 2.
+ * Outputs are host doubles. Synchronous.
+ */
+int ciq_eig_bounds(const ciq_problem* p, int dtype, int steps, const void* v0,
+                   uint64_t seed, double* lambda_min, double* lambda_max,
+                   hipStream_t stream);
+
+/*
+ * out = K^{-1/2} B (ciq_invsqrt_mvm) or K^{1/2} B (ciq_sqrt_mvm) by msMINRES-CIQ
+ * (Alg. S1; the square root multiplies the weighted solve sum by K once more,
+ * Sec. 3 rational approximation).
+ *   b: device n x s (ldb >= s); out: device n x s (ldo >= s).
+ *   solves: NULL, or device [n][q][s] (contiguous) receiving the per-shift
+ *     solutions x^{(q)} ~= (t_q I + K)^{-1} b, as needed by ciq_backward.
+ *   info: host, required.
+ * Stopping: per (shift, column) at |phibar|/||b_s|| <= tol, frozen thereafter;
+ * all at max_iter. A zero column of B gives a zero output column.
+ * Synchronous. Errors: CIQ_EINVAL (n, s, q, max_iter, tol, pointers, ldb/ldo,
+ * dtype/kernel/d out of range), CIQ_ENOMEM, CIQ_EHIP, CIQ_ENUMERIC.
+ */
+int ciq_invsqrt_mvm(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb,
+                    void* out, int ldo, void* solves, ciq_info* info, hipStream_t stream);
+int ciq_sqrt_mvm(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb,
+                 void* out, int ldo, void* solves, ciq_info* info, hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of a forward call made with the same p, shifts t/w
+ * (from its ciq_info) and its saved `solves` (Sec. 3.3):
+ *   g_q = (t_q I + K)^{-1} G' by one more msMINRES run, G' = G (invsqrt) or K G (sqrt),
+ *   dB  = sum_q w_q g_q,
+ *   dL/dK = -1/2 sum_q w_q (g_q a_q^T + a_q g_q^T)   [+ 1/2 (G A^T + A G^T) for sqrt],
+ * contracted on the fly with dK/dtheta (no N x N matrix is formed):
+ *   dlengthscale[n_lengthscale], doutputscale (d/d o^2), dnoise (d/d sigma^2).
+ *   g: device n x s (ldg >= s); db: device n x s (lddb >= s) or NULL;
+ *   each host gradient pointer may be NULL (then that contraction is skipped).
+ * Synchronous. Errors as for ciq_invsqrt_mvm.
+ */
+int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double* t,
+                 const double* w, const void* solves, const void* g, int s, int ldg,
+                 void* db, int lddb, double* dlengthscale, double* doutputscale,
+                 double* dnoise, ciq_info* info, hipStream_t stream);
+
+/*
+ * K_p^{-1/2} B_p for nprob independent problems of uneven n_p and d_p in one
+ * run: every iteration launches ONE kernel-product kernel that walks a work
+ * list over all problems, one reduction, one scalar and one update kernel;
+ * each problem has its own eigenvalue bounds, shifts, Lanczos and Givens state
+ * and stops on its own. All problems share kernel type, dtype (CIQ_F32), s, q.
+ *   probs: host array [nprob]; b, out: host arrays [nprob] of device pointers
+ *   (n_p x s, contiguous); infos: host array [nprob].
+ * Synchronous. Errors as for ciq_invsqrt_mvm.
+ */
+int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts* o,
+                            const void* const* b, int s, void* const* out,
+                            ciq_info* infos, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CIQ_H */

@@ -1,0 +1,153 @@
+// Internal declarations shared by the HIP kernels (kernels.hip) and the host
+// driver (host.cpp) of libciq. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "ciq.h"
+
+namespace ciq {
+
+// ---------------------------------------------------------------------------
+// Layout of one solver run (all device memory, carved from the scratch area).
+// Rows of every problem are concatenated: problem p owns rows
+// [row_off[p], row_off[p] + n[p]). Every n x s block vector is row-major with
+// leading dimension s ("point-major": a tile of rows is one contiguous span).
+// Global column index g = p * s + c. Per-shift arrays are indexed
+// [q * ncol + g]; shift tables [p * Q + q].
+// ---------------------------------------------------------------------------
+
+struct IterState {
+    int iter;       // msMINRES iterations done (products with K)
+    int done;       // 1 once every column stopped or iter reached the cap
+    int live;       // 1 if the current iteration's scalar stage ran
+    int numeric;    // 1 if a NaN/Inf Lanczos scalar was seen
+};
+
+struct ShiftCoef {          // per (shift, column), written by the scalar stage
+    double delta, eps, ginv, tau, tauw;
+    int upd;                // 1: this shift moves this iteration
+    int pad;
+};
+
+struct Dev {
+    // problem tables
+    int nprob, s, Q, ncol, max_iter;
+    int rows_total;         // sum of n over problems (stride of per-shift blocks)
+    const int* n;           // [nprob]
+    const int* row_off;     // [nprob]
+    const double* t;        // [nprob * Q]
+    const double* w;        // [nprob * Q]
+    double tol;
+    double bd_rtol;         // breakdown threshold relative to ||K q_j||
+    int bounds_mode;        // 1: plain Lanczos (no shifts), record T
+    // dots
+    int dots_blocks;        // partial blocks per problem
+    double* dots;           // [nprob][dots_blocks][s][2] (alpha, beta^2 partials)
+    // column state
+    double* beta1;          // ||b_g||
+    double* beta_cur;       // beta_j  (couples q_{j-1}, q_j)
+    double* alpha;          // alpha_j of the current iteration
+    double* beta_next;      // beta_{j+1}
+    double* inv_beta_next;  // 1 / beta_{j+1} (0 if the column stops)
+    double* beta_used;      // beta_j used in the current update
+    int* colflag;           // 0 idle, 1 update shifts only, 2 update + next Lanczos vector
+    int* colactive;         // column still iterating
+    int* col_iters;         // iterations per column
+    int* prob_done;         // [nprob]
+    double* T;              // bounds mode: [max_iter][ncol][2] (alpha, beta_next)
+    // shift state [Q * ncol]
+    double *c1, *s1, *c2, *s2, *phibar, *relres;
+    int* frozen;
+    ShiftCoef* coef;
+    IterState* st;
+};
+
+// Work list entry of the kernel-product kernel: (problem, row block).
+struct WorkItem {
+    int prob;
+    int rb;
+};
+
+// Arguments of one kernel-product launch Y = K V (split over the j range).
+struct MvmArgs {
+    const void* xh;          // scaled, zero-padded points: rows x dp
+    const void* v;           // rows x s (ld = ldv)
+    void* y;                 // partial outputs: nsplit x rows x s (ld = ldy)
+    long long ysplit;        // elements between split partials
+    int ldv, ldy;
+    int s;
+    int kernel;
+    int dp;
+    int nsplit;
+    // single problem (wl == nullptr)
+    int n;
+    double o2, s2;
+    // batched
+    const WorkItem* wl;      // [nrb_total]
+    int nrb;                 // number of row blocks (grid.x)
+    const int* pn;           // [nprob] n per problem
+    const int* poff;         // [nprob] row offset
+    const float* po2;        // [nprob]
+    const float* ps2;        // [nprob]
+    const int* prob_done;    // [nprob] or nullptr
+    const int* done;         // global done flag or nullptr
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+int mvm_rows_per_block(int dtype, int s);
+int mvm_pick_nsplit(int dtype, int nrb, int n_max);
+hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st);
+
+template <typename T>
+hipError_t launch_prep(const T* x, int n, int d, int dp, const double* scale, T* xh,
+                       hipStream_t st);
+
+template <typename T>
+hipError_t launch_reduce_splits(const T* ypart, long long ysplit, int nsplit, int ldy,
+                                int n, int s, T* out, int ldo, hipStream_t st);
+
+template <typename T>
+hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q,
+                       const T* qp, int phase, hipStream_t st);
+
+hipError_t launch_scalar_init(const Dev& d, hipStream_t st);
+hipError_t launch_scalar(const Dev& d, hipStream_t st);
+
+template <typename T>
+hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur,
+                         T* qprev, const T* m_prev, T* m_cur, T* acc, T* solves, int max_n,
+                         hipStream_t st);
+
+template <typename T>
+hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, int rows, hipStream_t st);
+
+template <typename T>
+hipError_t launch_copy_in(const T* src, int ld_src, int n, int s, T* dst, int ld_dst,
+                          hipStream_t st);
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t count, T value, hipStream_t st);
+
+template <typename T>
+hipError_t launch_splitmix(T* v, int n, uint64_t seed, int ld, hipStream_t st);
+
+// gradient tile pass: out[k] += sum_ij W_ij * dK_ij/dtheta_k, W = sum_q w_q G_q A_q^T
+struct GradArgs {
+    const float* xh;        // scaled points (kernel-specific scaling), n x dp
+    const float* xr;        // raw points scaled by 1/l (for (x_d - x'_d)^2 / l^2), n x dp
+    const float* gq;        // [n][Q][s] backward solves, pre-multiplied by w_q
+    const float* aq;        // [n][Q][s] forward solves
+    int n, dp, d, qs;       // qs = Q * s
+    int kernel;
+    double* partial;        // [gridDim.x * gridDim.y][d + 2]
+};
+hipError_t launch_grad_tiles(const GradArgs& a, int* nblocks_out, hipStream_t st);
+
+template <typename T>
+hipError_t launch_weighted_sum(const T* solves, int n, int Q, int s, const double* w_dev,
+                               T* out, int ldo, hipStream_t st);
+
+}  // namespace ciq

@@ -1,0 +1,144 @@
+// Host FP64 quadrature for K^{-1/2} (Appendix B; Alg. S2) and the small
+// symmetric eigensolver used by the extreme-eigenvalue estimate.
+#include <cmath>
+#include <vector>
+
+#include "ciq.h"
+
+namespace ciq {
+
+// Arithmetic-geometric mean of (1, b), 0 < b <= 1 (Abramowitz & Stegun 17.6).
+static double agm1(double b) {
+    double a = 1.0;
+    for (int it = 0; it < 64; ++it) {
+        const double an = 0.5 * (a + b);
+        const double bn = std::sqrt(a * b);
+        a = an;
+        b = bn;
+        if (std::fabs(a - b) <= 1e-17 * a) break;
+    }
+    return 0.5 * (a + b);
+}
+
+// Jacobi sn, cn, dn of (u | m) given b0 = sqrt(1 - m) and c0 = sqrt(m), by the
+// AGM / descending Landen scale (Abramowitz & Stegun 16.4): a_0 = 1, b_0, c_0;
+// a_n = (a + b)/2, b_n = sqrt(a b), c_n = c_{n-1}^2 / (4 a_n); phi_N = 2^N a_N u;
+// phi_{n-1} = (phi_n + asin(c_n sin(phi_n) / a_n)) / 2. dn is taken from
+// dn^2 = cn^2 + b0^2 sn^2, which has no cancellation as m -> 1.
+static void jacobi_sncndn(double u, double b0, double c0, double* sn, double* cn, double* dn) {
+    double a[40], c[40];
+    a[0] = 1.0;
+    c[0] = c0;
+    double b = b0;
+    int N = 0;
+    while (N < 38) {
+        const double an = 0.5 * (a[N] + b);
+        const double bn = std::sqrt(a[N] * b);
+        const double cn_ = c[N] * c[N] / (4.0 * an);
+        ++N;
+        a[N] = an;
+        c[N] = cn_;
+        b = bn;
+        if (std::fabs(cn_) <= 1e-18 * an) break;
+    }
+    double phi = std::ldexp(a[N] * u, N);
+    for (int n = N; n >= 1; --n) phi = 0.5 * (phi + std::asin(c[n] * std::sin(phi) / a[n]));
+    *sn = std::sin(phi);
+    *cn = std::cos(phi);
+    *dn = std::sqrt((*cn) * (*cn) + b0 * b0 * (*sn) * (*sn));
+}
+
+// Shifts and weights of the HHT rule (positive pair of Appendix B):
+//   k^2 = lmin/lmax, K' = K(k') = pi / (2 AGM(1, k)),
+//   (sn, cn, dn) = (sn, cn, dn)(u_q K' | k'^2),  u_q = (q - 1/2)/Q,
+//   t_q = lmin (sn/cn)^2,  w_q = 2 sqrt(lmin) K' dn / (pi Q cn^2).
+// For u_q > 1/2 the quarter-period reflection (A&S 16.8: sn(K - v) = cn v/dn v,
+// cn(K - v) = k sn v / dn v, dn(K - v) = k / dn v, with k the complementary
+// modulus of k') is used with v = (1 - u_q) K', so the small cn is formed
+// without cancellation:
+//   t_q = lmax (cn_v / sn_v)^2,   w_q = 2 sqrt(lmax) K' dn_v / (pi Q sn_v^2).
+int hht_quadrature(double lmin, double lmax, int Q, double* t, double* w) {
+    const double k = std::sqrt(lmin / lmax);                   // modulus k
+    const double kp = std::sqrt((1.0 - k) * (1.0 + k));         // complementary k'
+    const double Kp = M_PI / (2.0 * agm1(k));                   // K(k') with b0 = sqrt(1 - k'^2) = k
+    for (int q = 1; q <= Q; ++q) {
+        const double uq = (q - 0.5) / Q;
+        double sn, cn, dn;
+        if (uq <= 0.5) {
+            jacobi_sncndn(uq * Kp, k, kp, &sn, &cn, &dn);
+            t[q - 1] = lmin * (sn / cn) * (sn / cn);
+            w[q - 1] = 2.0 * std::sqrt(lmin) * Kp * dn / (M_PI * Q * cn * cn);
+        } else {
+            const double v = ((Q - q + 0.5) / Q) * Kp;
+            jacobi_sncndn(v, k, kp, &sn, &cn, &dn);
+            t[q - 1] = lmax * (cn / sn) * (cn / sn);
+            w[q - 1] = 2.0 * std::sqrt(lmax) * Kp * dn / (M_PI * Q * sn * sn);
+        }
+    }
+    return CIQ_OK;
+}
+
+// Eigenvalues/vectors of a small symmetric matrix (row-major n x n) by cyclic
+// Jacobi rotations (Golub & Van Loan 8.5). Eigenvector j is column j of v.
+void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& evals, std::vector<double>& v) {
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    double norm = 0.0;
+    for (double x : a) norm += x * x;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += a[(size_t)i * n + j] * a[(size_t)i * n + j];
+        if (off <= 1e-30 * norm || off == 0.0) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(tt * tt + 1.0), s = tt * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = c * akp - s * akq;
+                    a[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = c * apk - s * aqk;
+                    a[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+                    v[(size_t)k * n + p] = c * vkp - s * vkq;
+                    v[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    evals.resize(n);
+    for (int i = 0; i < n; ++i) evals[i] = a[(size_t)i * n + i];
+}
+
+// Widened bounds from a Lanczos tridiagonal (alpha[0..J), beta[0..J), beta[J-1]
+// the final residual norm): lambda_max = theta_max + beta_{J+1} |y_J|,
+// lambda_min = min(theta_min, noise) if noise > 0, else theta_min / 2.
+void bounds_from_tridiag(int J, const double* alpha, const double* beta, double noise, double* lmin,
+                         double* lmax) {
+    std::vector<double> a((size_t)J * J, 0.0), ev, v;
+    for (int i = 0; i < J; ++i) {
+        a[(size_t)i * J + i] = alpha[i];
+        if (i + 1 < J) a[(size_t)i * J + i + 1] = a[(size_t)(i + 1) * J + i] = beta[i];
+    }
+    sym_eig_jacobi(J, a, ev, v);
+    int imin = 0, imax = 0;
+    for (int i = 1; i < J; ++i) {
+        if (ev[i] < ev[imin]) imin = i;
+        if (ev[i] > ev[imax]) imax = i;
+    }
+    const double ylast = v[(size_t)(J - 1) * J + imax];
+    *lmax = ev[imax] + std::fabs(beta[J - 1] * ylast);
+    *lmin = (noise > 0.0) ? std::fmin(ev[imin], noise) : 0.5 * ev[imin];
+}
+
+}  // namespace ciq

@@ -1,0 +1,775 @@
+// Host driver and C ABI of libciq.
+//
+// One solver call: validate -> scale/pad points on the device -> (optional)
+// Lanczos extreme-eigenvalue estimate -> HHT shifts/weights on the host ->
+// msMINRES loop (per iteration: kernel product, six-dot reduction, scalar
+// Givens stage, fused vector update; all queued on the caller's stream, the
+// host polls a device "done" flag every few iterations) -> combine.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "ciq.h"
+#include "ciq_internal.h"
+
+namespace ciq {
+int hht_quadrature(double lmin, double lmax, int Q, double* t, double* w);
+void bounds_from_tridiag(int J, const double* alpha, const double* beta, double noise, double* lmin,
+                         double* lmax);
+}  // namespace ciq
+
+using namespace ciq;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr double kSqrt5 = 2.23606797749978969640917366873;
+constexpr double kLog2e = 1.44269504088896340735992468100;
+
+#define HIPCHK(expr)                        \
+    do {                                    \
+        hipError_t e_ = (expr);             \
+        if (e_ != hipSuccess) return CIQ_EHIP; \
+    } while (0)
+
+#define STCHK(expr)                 \
+    do {                            \
+        int s_ = (expr);            \
+        if (s_ != CIQ_OK) return s_; \
+    } while (0)
+
+// ---- per-device grow-only scratch ---------------------------------------
+struct DeviceScratch {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    IterState* pinned = nullptr;  // host-pinned mirror of the iteration state
+    std::mutex mu;
+};
+DeviceScratch g_scratch[kMaxDevices];
+
+int scratch_reserve(int dev, size_t bytes, void** out) {
+    DeviceScratch& sc = g_scratch[dev];
+    if (sc.cap < bytes) {
+        if (sc.ptr) {
+            HIPCHK(hipDeviceSynchronize());
+            HIPCHK(hipFree(sc.ptr));
+            sc.ptr = nullptr;
+            sc.cap = 0;
+        }
+        size_t want = bytes + bytes / 4 + (1 << 20);
+        if (hipMalloc(&sc.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            sc.ptr = nullptr;
+            if (hipMalloc(&sc.ptr, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                sc.ptr = nullptr;
+                return CIQ_ENOMEM;
+            }
+            want = bytes;
+        }
+        sc.cap = want;
+    }
+    if (!sc.pinned) {
+        if (hipHostMalloc((void**)&sc.pinned, sizeof(IterState), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            sc.pinned = nullptr;
+            return CIQ_ENOMEM;
+        }
+    }
+    *out = sc.ptr;
+    return CIQ_OK;
+}
+
+// Bump allocator over the scratch area (256-byte aligned pieces).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+// Same layout arithmetic without a base pointer (to size the scratch first).
+struct Sizer {
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        off += count * sizeof(T);
+        return nullptr;
+    }
+};
+
+int pad_dims(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : 16; }
+
+bool valid_problem(const ciq_problem* p) {
+    if (!p || !p->x || !p->lengthscale) return false;
+    if (p->n < 1 || p->d < 1 || p->d > CIQ_MAX_D) return false;
+    if (p->kernel != CIQ_KERNEL_RBF && p->kernel != CIQ_KERNEL_MATERN52) return false;
+    if (p->n_lengthscale != 1 && p->n_lengthscale != p->d) return false;
+    for (int k = 0; k < p->n_lengthscale; ++k)
+        if (!(p->lengthscale[k] > 0.0) || !std::isfinite(p->lengthscale[k])) return false;
+    if (!(p->outputscale > 0.0) || !std::isfinite(p->outputscale)) return false;
+    if (!(p->noise >= 0.0) || !std::isfinite(p->noise)) return false;
+    return true;
+}
+
+bool valid_dtype(int dt) { return dt == CIQ_F64 || dt == CIQ_F32 || dt == CIQ_BF16X3 || dt == CIQ_F16X3; }
+
+// Per-dimension multipliers applied to X so the device kernels evaluate k from
+// a plain squared distance (see kfun32 / kfun64 in kernels.hip).
+void point_scale(const ciq_problem* p, int dtype, double* scale) {
+    double c;
+    if (p->kernel == CIQ_KERNEL_RBF)
+        c = (dtype == CIQ_F64) ? 1.0 : std::sqrt(0.5 * kLog2e);
+    else
+        c = kSqrt5;
+    for (int k = 0; k < p->d; ++k) {
+        const double l = p->lengthscale[p->n_lengthscale == 1 ? 0 : k];
+        scale[k] = c / l;
+    }
+}
+
+int get_device(int* dev) {
+    HIPCHK(hipGetDevice(dev));
+    if (*dev < 0 || *dev >= kMaxDevices) return CIQ_EINVAL;
+    return CIQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One Krylov run over nprob problems (the single-problem calls use nprob = 1).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Run {
+    int dtype = CIQ_F32, kernel = 0, dp = 4;
+    int nprob = 1, s = 1, Q = 0, max_iter = 0, rows_total = 0, max_n = 0;
+    double tol = 0.0;
+    int bounds_mode = 0;
+    int nsplit = 1, nrb = 0;
+    bool keep_solves = false;
+    // device memory
+    T* xh = nullptr;
+    T* qbuf[2] = {nullptr, nullptr};
+    T* ypart = nullptr;
+    T* mbuf[2] = {nullptr, nullptr};
+    T* acc = nullptr;
+    T* solves = nullptr;  // [rows][Q][s]
+    WorkItem* wl = nullptr;
+    int* pn = nullptr;
+    int* poff = nullptr;
+    float* po2 = nullptr;
+    float* ps2 = nullptr;
+    double* t = nullptr;
+    double* w = nullptr;
+    Dev d{};
+    long long ysplit = 0;
+    // host mirrors
+    std::vector<int> h_n, h_off;
+    std::vector<float> h_o2, h_s2;
+    std::vector<double> h_o2d, h_s2d;
+
+    template <typename A>
+    void layout(A& a, bool with_xh) {
+        const int ncol = nprob * s;
+        const size_t vec = (size_t)rows_total * s;
+        if (with_xh) xh = a.template take<T>((size_t)rows_total * dp);
+        qbuf[0] = a.template take<T>(vec);
+        qbuf[1] = a.template take<T>(vec);
+        ypart = a.template take<T>(vec * nsplit);
+        if (Q > 0) {
+            mbuf[0] = a.template take<T>(vec * Q);
+            mbuf[1] = a.template take<T>(vec * Q);
+        }
+        acc = a.template take<T>(vec);
+        if (keep_solves) solves = a.template take<T>(vec * Q);
+        wl = a.template take<WorkItem>(std::max(nrb, 1));
+        pn = a.template take<int>(nprob);
+        poff = a.template take<int>(nprob);
+        po2 = a.template take<float>(nprob);
+        ps2 = a.template take<float>(nprob);
+        t = a.template take<double>(std::max(nprob * Q, 1));
+        w = a.template take<double>(std::max(nprob * Q, 1));
+        d.dots = a.template take<double>((size_t)nprob * d.dots_blocks * s * 2);
+        d.beta1 = a.template take<double>(ncol);
+        d.beta_cur = a.template take<double>(ncol);
+        d.alpha = a.template take<double>(ncol);
+        d.beta_next = a.template take<double>(ncol);
+        d.inv_beta_next = a.template take<double>(ncol);
+        d.beta_used = a.template take<double>(ncol);
+        d.colflag = a.template take<int>(ncol);
+        d.colactive = a.template take<int>(ncol);
+        d.col_iters = a.template take<int>(ncol);
+        d.prob_done = a.template take<int>(nprob);
+        d.T = bounds_mode ? a.template take<double>((size_t)std::max(max_iter, 1) * ncol * 2) : nullptr;
+        const size_t qn = (size_t)std::max(Q, 1) * ncol;
+        d.c1 = a.template take<double>(qn);
+        d.s1 = a.template take<double>(qn);
+        d.c2 = a.template take<double>(qn);
+        d.s2 = a.template take<double>(qn);
+        d.phibar = a.template take<double>(qn);
+        d.relres = a.template take<double>(qn);
+        d.frozen = a.template take<int>(qn);
+        d.coef = a.template take<ShiftCoef>(qn);
+        d.st = a.template take<IterState>(1);
+    }
+
+    void configure(int rows_per_block) {
+        int rows_per_blk_dots = 256 / std::max(1, std::min(64, s));
+        (void)rows_per_blk_dots;
+        d.dots_blocks = std::min(64, std::max(1, (max_n + 255) / 256));
+        nrb = 0;
+        for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rows_per_block - 1) / rows_per_block;
+        nsplit = mvm_pick_nsplit(dtype, nrb, max_n);
+        ysplit = (long long)rows_total * s;
+    }
+
+    void fill_dev() {
+        d.nprob = nprob;
+        d.s = s;
+        d.Q = Q;
+        d.ncol = nprob * s;
+        d.max_iter = max_iter;
+        d.rows_total = rows_total;
+        d.n = pn;
+        d.row_off = poff;
+        d.t = t;
+        d.w = w;
+        d.tol = tol;
+        d.bd_rtol = (dtype == CIQ_F64) ? 1e-13 : 1e-6;
+        d.bounds_mode = bounds_mode;
+    }
+
+    int upload_tables(hipStream_t st, int rows_per_block) {
+        std::vector<WorkItem> h_wl;
+        for (int p = 0; p < nprob; ++p) {
+            const int nb = (h_n[p] + rows_per_block - 1) / rows_per_block;
+            for (int r = 0; r < nb; ++r) h_wl.push_back(WorkItem{p, r});
+        }
+        HIPCHK(hipMemcpyAsync(wl, h_wl.data(), h_wl.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pn, h_n.data(), nprob * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(poff, h_off.data(), nprob * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(po2, h_o2.data(), nprob * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ps2, h_s2.data(), nprob * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // host vectors are pageable and short-lived
+        return CIQ_OK;
+    }
+
+    MvmArgs mvm_args(const T* v, T* y) const {
+        MvmArgs a{};
+        a.xh = xh;
+        a.v = v;
+        a.y = y;
+        a.ysplit = ysplit;
+        a.ldv = s;
+        a.ldy = s;
+        a.s = s;
+        a.kernel = kernel;
+        a.dp = dp;
+        a.nsplit = nsplit;
+        a.n = h_n[0];
+        a.o2 = h_o2d[0];
+        a.s2 = h_s2d[0];
+        a.wl = (nprob > 1) ? wl : nullptr;
+        a.nrb = nrb;
+        a.pn = pn;
+        a.poff = poff;
+        a.po2 = po2;
+        a.ps2 = ps2;
+        a.prob_done = (nprob > 1) ? d.prob_done : nullptr;
+        a.done = &d.st->done;
+        return a;
+    }
+
+    // Krylov iterations after the start vectors are in qbuf[0]. Returns status.
+    int iterate(hipStream_t st, int check_every, IterState* pinned, int* mvm_count,
+                hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed) {
+        HIPCHK(launch_dots<T>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
+        HIPCHK(launch_scalar_init(d, st));
+        if (Q > 0) {
+            HIPCHK(launch_fill<T>(mbuf[0], (size_t)rows_total * s * Q, (T)0, st));
+            HIPCHK(launch_fill<T>(mbuf[1], (size_t)rows_total * s * Q, (T)0, st));
+        }
+        if (solves) HIPCHK(launch_fill<T>(solves, (size_t)rows_total * s * Q, (T)0, st));
+        HIPCHK(launch_init_vectors<T>(d, qbuf[0], qbuf[1], acc, rows_total, st));
+        int j = 1;
+        int pending = 0;
+        while (j <= max_iter) {
+            T* qcur = qbuf[(j - 1) & 1];
+            T* qprv = qbuf[j & 1];
+            T* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
+            T* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
+            const bool timed = ev_pool != nullptr && pending < n_ev;
+            if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
+            HIPCHK(launch_mvm(dtype, mvm_args(qcur, ypart), st));
+            if (timed) {
+                HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
+                ++pending;
+            }
+            HIPCHK(launch_dots<T>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+            HIPCHK(launch_dots<T>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+            HIPCHK(launch_scalar(d, st));
+            HIPCHK(launch_update<T>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, max_n, st));
+            if (j % check_every == 0 || j == max_iter) {
+                HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (ev_pool) {
+                    // only launches issued while the run was still live count; the
+                    // device-side early exit after `done` is not a kernel product
+                    const int live = std::min(pending, pinned->iter - *mvm_timed);
+                    for (int k = 0; k < live; ++k) {
+                        float ms = 0.f;
+                        HIPCHK(hipEventElapsedTime(&ms, ev_pool[2 * k], ev_pool[2 * k + 1]));
+                        *mvm_ms += ms;
+                    }
+                    *mvm_timed += std::max(live, 0);
+                    pending = 0;
+                }
+                if (pinned->numeric) return CIQ_ENUMERIC;
+                if (pinned->done) break;
+            }
+            ++j;
+        }
+        HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (pinned->numeric) return CIQ_ENUMERIC;
+        *mvm_count += pinned->iter;
+        return CIQ_OK;
+    }
+
+    // Slot of the final iterate's Lanczos vector etc. is irrelevant to callers:
+    // the combined solution lives in acc, the per-shift solves in `solves`.
+};
+
+template <typename T>
+int setup_points(Run<T>& r, const ciq_problem* probs, int dtype, hipStream_t st) {
+    for (int p = 0; p < r.nprob; ++p) {
+        double scale[CIQ_MAX_D];
+        point_scale(&probs[p], dtype, scale);
+        HIPCHK(launch_prep<T>(static_cast<const T*>(probs[p].x), probs[p].n, probs[p].d, r.dp, scale,
+                              r.xh + (size_t)r.h_off[p] * r.dp, st));
+    }
+    return CIQ_OK;
+}
+
+template <typename T>
+void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob) {
+    r.nprob = nprob;
+    r.h_n.resize(nprob);
+    r.h_off.resize(nprob);
+    r.h_o2.resize(nprob);
+    r.h_s2.resize(nprob);
+    r.h_o2d.resize(nprob);
+    r.h_s2d.resize(nprob);
+    int off = 0, maxn = 0, maxd = 1;
+    for (int p = 0; p < nprob; ++p) {
+        r.h_n[p] = probs[p].n;
+        r.h_off[p] = off;
+        off += probs[p].n;
+        maxn = std::max(maxn, probs[p].n);
+        maxd = std::max(maxd, probs[p].d);
+        r.h_o2[p] = (float)probs[p].outputscale;
+        r.h_s2[p] = (float)probs[p].noise;
+        r.h_o2d[p] = probs[p].outputscale;
+        r.h_s2d[p] = probs[p].noise;
+    }
+    r.rows_total = off;
+    r.max_n = maxn;
+    r.dp = pad_dims(maxd);
+    r.kernel = probs[0].kernel;
+}
+
+struct ScratchLock {
+    std::unique_lock<std::mutex> lk;
+    explicit ScratchLock(int dev) : lk(g_scratch[dev].mu) {}
+};
+
+// Full CIQ solve for nprob problems sharing s, Q, dtype, kernel.
+// out_ptrs[p]: n_p x s with leading dimension ldo; b_ptrs likewise with ldb.
+template <typename T>
+int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* const* b_ptrs, int s, int ldb,
+          void* const* out_ptrs, int ldo, void* solves_out, int mode, ciq_info* infos, hipStream_t st) {
+    int dev;
+    STCHK(get_device(&dev));
+    ScratchLock lock(dev);
+    const int dtype = o->dtype;
+    const int check_every = o->check_every > 0 ? o->check_every : 16;
+    const int steps = o->lanczos_steps > 0 ? o->lanczos_steps : 20;
+    const bool have_bounds = o->lambda_min > 0.0 && o->lambda_max >= o->lambda_min &&
+                             std::isfinite(o->lambda_max);
+    const bool profile = o->profile != 0;
+
+    // ---- sizing: bounds run (s = 1, Q = 0) and main run share the points ----
+    Run<T> main;
+    fill_problem_tables(main, probs, nprob);
+    main.dtype = dtype;
+    main.s = s;
+    main.Q = o->q;
+    main.max_iter = o->max_iter;
+    main.tol = o->tol;
+    main.keep_solves = (solves_out != nullptr);
+    const int rpb_main = mvm_rows_per_block(dtype, s);
+    main.configure(rpb_main);
+
+    Run<T> bnd;
+    fill_problem_tables(bnd, probs, nprob);
+    bnd.dtype = dtype;
+    bnd.s = 1;
+    bnd.Q = 0;
+    bnd.max_iter = steps;
+    bnd.tol = 0.0;
+    bnd.bounds_mode = 1;
+    const int rpb_b = mvm_rows_per_block(dtype, 1);
+    bnd.configure(rpb_b);
+
+    Sizer sz;
+    main.layout(sz, true);
+    const size_t off_after_xh = 0;
+    (void)off_after_xh;
+    Sizer szb;
+    szb.take<T>((size_t)main.rows_total * main.dp);
+    bnd.layout(szb, false);
+    const size_t need = std::max(sz.off, szb.off) + 4096;
+    void* base = nullptr;
+    STCHK(scratch_reserve(dev, need, &base));
+    IterState* pinned = g_scratch[dev].pinned;
+
+    Carver cm(base);
+    main.layout(cm, true);
+    Carver cb(base);
+    bnd.xh = cb.take<T>((size_t)main.rows_total * main.dp);
+    bnd.layout(cb, false);
+    main.fill_dev();
+    bnd.fill_dev();
+
+    STCHK(main.upload_tables(st, rpb_main));
+    STCHK(setup_points(main, probs, dtype, st));
+
+    std::vector<double> lmin(nprob), lmax(nprob);
+    int mvm_count = 0;
+    double mvm_ms = 0.0;
+    int mvm_timed = 0;
+    std::vector<hipEvent_t> evs;
+    if (profile) {
+        evs.resize(2 * check_every);
+        for (auto& e : evs) HIPCHK(hipEventCreate(&e));
+    }
+    struct EvGuard {
+        std::vector<hipEvent_t>& v;
+        ~EvGuard() {
+            for (auto e : v) (void)hipEventDestroy(e);
+        }
+    } evguard{evs};
+
+    if (have_bounds) {
+        for (int p = 0; p < nprob; ++p) {
+            lmin[p] = o->lambda_min;
+            lmax[p] = o->lambda_max;
+        }
+    } else {
+        STCHK(bnd.upload_tables(st, rpb_b));
+        for (int p = 0; p < nprob; ++p)
+            HIPCHK(launch_splitmix<T>(bnd.qbuf[0] + bnd.h_off[p], bnd.h_n[p], o->seed + 7919ull * p, 1, st));
+        int cnt = 0, dummy_n = 0;
+        double dummy = 0.0;
+        STCHK(bnd.iterate(st, std::max(steps, 1), pinned, &cnt, nullptr, 0, &dummy, &dummy_n));
+        mvm_count += cnt;
+        const int J = pinned->iter;
+        std::vector<double> Th((size_t)std::max(J, 1) * nprob * 2);
+        if (J > 0)
+            HIPCHK(hipMemcpyAsync(Th.data(), bnd.d.T, Th.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        std::vector<int> citers(nprob);
+        HIPCHK(hipMemcpyAsync(citers.data(), bnd.d.col_iters, nprob * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int p = 0; p < nprob; ++p) {
+            const int Jp = std::max(1, citers[p]);
+            std::vector<double> al(Jp), be(Jp);
+            for (int j = 0; j < Jp; ++j) {
+                al[j] = Th[((size_t)j * nprob + p) * 2 + 0];
+                be[j] = Th[((size_t)j * nprob + p) * 2 + 1];
+            }
+            bounds_from_tridiag(Jp, al.data(), be.data(), probs[p].noise, &lmin[p], &lmax[p]);
+            if (!(lmin[p] > 0.0) || !(lmax[p] >= lmin[p]) || !std::isfinite(lmax[p])) return CIQ_ENUMERIC;
+        }
+        // the bounds run reused the scratch after the points; restore the main tables
+        STCHK(main.upload_tables(st, rpb_main));
+    }
+
+    // ---- shifts / weights --------------------------------------------------
+    std::vector<double> th((size_t)nprob * main.Q), wh((size_t)nprob * main.Q);
+    for (int p = 0; p < nprob; ++p) {
+        const int rc = ciq_setup(lmin[p], lmax[p], main.Q, &th[(size_t)p * main.Q], &wh[(size_t)p * main.Q]);
+        if (rc != CIQ_OK) return CIQ_ENUMERIC;
+    }
+    HIPCHK(hipMemcpyAsync(main.t, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(main.w, wh.data(), wh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+
+    // ---- right-hand sides --------------------------------------------------
+    for (int p = 0; p < nprob; ++p)
+        HIPCHK(launch_copy_in<T>(static_cast<const T*>(b_ptrs[p]), ldb, main.h_n[p], s,
+                                 main.qbuf[0] + (size_t)main.h_off[p] * s, s, st));
+    HIPCHK(hipStreamSynchronize(st));  // th/wh are pageable host vectors
+
+    STCHK(main.iterate(st, check_every, pinned, &mvm_count, profile ? evs.data() : nullptr,
+                       profile ? check_every : 0, &mvm_ms, &mvm_timed));
+    const int iters = pinned->iter;
+
+    // ---- combine -----------------------------------------------------------
+    if (mode == CIQ_SQRT) {
+        HIPCHK(launch_mvm(dtype, [&] {
+            MvmArgs a = main.mvm_args(main.acc, main.ypart);
+            a.done = nullptr;
+            a.prob_done = nullptr;
+            return a;
+        }(), st));
+        mvm_count += 1;
+        for (int p = 0; p < nprob; ++p)
+            HIPCHK(launch_reduce_splits<T>(main.ypart + (size_t)main.h_off[p] * s, main.ysplit, main.nsplit, s,
+                                           main.h_n[p], s, static_cast<T*>(out_ptrs[p]), ldo, st));
+    } else {
+        for (int p = 0; p < nprob; ++p)
+            HIPCHK(launch_copy_in<T>(main.acc + (size_t)main.h_off[p] * s, s, main.h_n[p], s,
+                                     static_cast<T*>(out_ptrs[p]), ldo, st));
+    }
+    if (solves_out) {
+        HIPCHK(hipMemcpyAsync(solves_out, main.solves, (size_t)main.rows_total * main.Q * s * sizeof(T),
+                              hipMemcpyDeviceToDevice, st));
+    }
+
+    // ---- report ------------------------------------------------------------
+    const int ncol = nprob * s;
+    const size_t qn = (size_t)main.Q * ncol;
+    std::vector<int> frozen(qn), citers(ncol);
+    std::vector<double> relres(qn);
+    if (qn) {
+        HIPCHK(hipMemcpyAsync(frozen.data(), main.d.frozen, qn * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(relres.data(), main.d.relres, qn * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(citers.data(), main.d.col_iters, ncol * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int p = 0; p < nprob; ++p) {
+        ciq_info& in = infos[p];
+        std::memset(&in, 0, sizeof(in));
+        int it = 0, conv = 1;
+        double mr = 0.0;
+        for (int c = 0; c < s; ++c) {
+            const int g = p * s + c;
+            it = std::max(it, citers[g]);
+            for (int q = 0; q < main.Q; ++q) {
+                const size_t idx = (size_t)q * ncol + g;
+                mr = std::max(mr, relres[idx]);
+                if (!(relres[idx] <= main.tol)) conv = 0;
+            }
+        }
+        in.iters = (nprob == 1) ? iters : it;
+        in.converged = conv;
+        in.q = main.Q;
+        in.mvm_count = mvm_count;
+        in.max_rel_residual = mr;
+        in.lambda_min = lmin[p];
+        in.lambda_max = lmax[p];
+        for (int q = 0; q < main.Q; ++q) {
+            in.t[q] = th[(size_t)p * main.Q + q];
+            in.w[q] = wh[(size_t)p * main.Q + q];
+        }
+        in.mvm_ms = mvm_ms;
+        in.mvm_timed = mvm_timed;
+    }
+    return CIQ_OK;
+}
+
+int check_solve_args(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb, void* out,
+                     int ldo, ciq_info* info) {
+    if (!valid_problem(p) || !o || !b || !out || !info) return CIQ_EINVAL;
+    if (!valid_dtype(o->dtype)) return CIQ_EINVAL;
+    if (s < 1 || ldb < s || ldo < s) return CIQ_EINVAL;
+    if (o->q < 1 || o->q > CIQ_MAX_Q || o->max_iter < 1) return CIQ_EINVAL;
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return CIQ_EINVAL;
+    if (o->lanczos_steps < 0 || o->check_every < 0) return CIQ_EINVAL;
+    return CIQ_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+int ciq_version(void) { return 100; }
+
+const char* ciq_strerror(int status) {
+    switch (status) {
+        case CIQ_OK: return "CIQ_OK";
+        case CIQ_EINVAL: return "CIQ_EINVAL: invalid argument";
+        case CIQ_ENOMEM: return "CIQ_ENOMEM: device scratch allocation failed";
+        case CIQ_EHIP: return "CIQ_EHIP: HIP runtime error";
+        case CIQ_ENOTSUP: return "CIQ_ENOTSUP: not supported by this build";
+        case CIQ_ENUMERIC: return "CIQ_ENUMERIC: non-finite Lanczos scalar";
+        default: return "CIQ: unknown status";
+    }
+}
+
+int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double* w_out) {
+    if (!t_out || !w_out || q < 1 || q > CIQ_MAX_Q) return CIQ_EINVAL;
+    if (!(lambda_min > 0.0) || !(lambda_max >= lambda_min) || !std::isfinite(lambda_max)) return CIQ_EINVAL;
+    return ciq::hht_quadrature(lambda_min, lambda_max, q, t_out, w_out);
+}
+
+int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,
+                   hipStream_t stream) {
+    if (!valid_problem(p) || !valid_dtype(dtype) || !v || !y || s < 1 || ldv < s || ldy < s) return CIQ_EINVAL;
+    if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) return CIQ_ENOTSUP;
+    const int dp = pad_dims(p->d);
+    const size_t esz = (dtype == CIQ_F64) ? 8 : 4;
+    const int rpb = mvm_rows_per_block(dtype, s);
+    const int nrb = (p->n + rpb - 1) / rpb;
+    const int nsplit = mvm_pick_nsplit(dtype, nrb, p->n);
+    // stream-ordered scratch: scaled points (+ split partials when nsplit > 1)
+    const size_t xbytes = ((size_t)p->n * dp * esz + 255) & ~size_t(255);
+    const size_t ybytes = (nsplit > 1) ? (size_t)nsplit * p->n * s * esz : 0;
+    void* buf = nullptr;
+    if (hipMallocAsync(&buf, xbytes + ybytes, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return CIQ_ENOMEM;
+    }
+    double scale[CIQ_MAX_D];
+    point_scale(p, dtype, scale);
+    hipError_t e;
+    if (dtype == CIQ_F64)
+        e = launch_prep<double>(static_cast<const double*>(p->x), p->n, p->d, dp, scale, static_cast<double*>(buf),
+                                stream);
+    else
+        e = launch_prep<float>(static_cast<const float*>(p->x), p->n, p->d, dp, scale, static_cast<float*>(buf),
+                               stream);
+    if (e != hipSuccess) return CIQ_EHIP;
+    MvmArgs a{};
+    a.xh = buf;
+    a.v = v;
+    a.y = (nsplit > 1) ? static_cast<void*>(static_cast<char*>(buf) + xbytes) : y;
+    a.ysplit = (nsplit > 1) ? (long long)p->n * s : 0;
+    a.ldv = ldv;
+    a.ldy = (nsplit > 1) ? s : ldy;
+    a.s = s;
+    a.kernel = p->kernel;
+    a.dp = dp;
+    a.nsplit = nsplit;
+    a.n = p->n;
+    a.o2 = p->outputscale;
+    a.s2 = p->noise;
+    a.nrb = nrb;
+    if (launch_mvm(dtype, a, stream) != hipSuccess) return CIQ_EHIP;
+    if (nsplit > 1) {
+        if (dtype == CIQ_F64)
+            e = launch_reduce_splits<double>(static_cast<const double*>(a.y), a.ysplit, nsplit, s, p->n, s,
+                                             static_cast<double*>(y), ldy, stream);
+        else
+            e = launch_reduce_splits<float>(static_cast<const float*>(a.y), a.ysplit, nsplit, s, p->n, s,
+                                            static_cast<float*>(y), ldy, stream);
+        if (e != hipSuccess) return CIQ_EHIP;
+    }
+    if (hipFreeAsync(buf, stream) != hipSuccess) return CIQ_EHIP;
+    return CIQ_OK;
+}
+
+int ciq_eig_bounds(const ciq_problem* p, int dtype, int steps, const void* v0, uint64_t seed,
+                   double* lambda_min, double* lambda_max, hipStream_t stream) {
+    if (!valid_problem(p) || !valid_dtype(dtype) || !lambda_min || !lambda_max || steps < 0) return CIQ_EINVAL;
+    if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) dtype = CIQ_F32;
+    int dev;
+    STCHK(get_device(&dev));
+    ScratchLock lock(dev);
+    const int J = steps > 0 ? steps : 20;
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        Run<T> r;
+        fill_problem_tables(r, p, 1);
+        r.dtype = dtype;
+        r.s = 1;
+        r.Q = 0;
+        r.max_iter = J;
+        r.bounds_mode = 1;
+        const int rpb = mvm_rows_per_block(dtype, 1);
+        r.configure(rpb);
+        Sizer sz;
+        r.layout(sz, true);
+        void* base = nullptr;
+        STCHK(scratch_reserve(dev, sz.off + 4096, &base));
+        Carver c(base);
+        r.layout(c, true);
+        r.fill_dev();
+        STCHK(r.upload_tables(stream, rpb));
+        STCHK(setup_points(r, p, dtype, stream));
+        if (v0)
+            HIPCHK(launch_copy_in<T>(static_cast<const T*>(v0), 1, p->n, 1, r.qbuf[0], 1, stream));
+        else
+            HIPCHK(launch_splitmix<T>(r.qbuf[0], p->n, seed, 1, stream));
+        int cnt = 0, dummy_n = 0;
+        double dummy = 0.0;
+        IterState* pinned = g_scratch[dev].pinned;
+        STCHK(r.iterate(stream, J, pinned, &cnt, nullptr, 0, &dummy, &dummy_n));
+        int Jp = 0;
+        HIPCHK(hipMemcpy(&Jp, r.d.col_iters, sizeof(int), hipMemcpyDeviceToHost));
+        Jp = std::max(Jp, 1);
+        std::vector<double> Th((size_t)Jp * 2);
+        HIPCHK(hipMemcpy(Th.data(), r.d.T, Th.size() * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<double> al(Jp), be(Jp);
+        for (int j = 0; j < Jp; ++j) {
+            al[j] = Th[2 * j];
+            be[j] = Th[2 * j + 1];
+        }
+        bounds_from_tridiag(Jp, al.data(), be.data(), p->noise, lambda_min, lambda_max);
+        return CIQ_OK;
+    };
+    if (dtype == CIQ_F64) return run(double{});
+    return run(float{});
+}
+
+static int solve_single(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb, void* out, int ldo,
+                        void* solves, ciq_info* info, hipStream_t stream, int mode) {
+    const int rc = check_solve_args(p, o, b, s, ldb, out, ldo, info);
+    if (rc != CIQ_OK) return rc;
+    const void* bp[1] = {b};
+    void* op[1] = {out};
+    if (o->dtype == CIQ_F64) return solve<double>(1, p, o, bp, s, ldb, op, ldo, solves, mode, info, stream);
+    if (o->dtype == CIQ_F32) return solve<float>(1, p, o, bp, s, ldb, op, ldo, solves, mode, info, stream);
+    return CIQ_ENOTSUP;
+}
+
+int ciq_invsqrt_mvm(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb, void* out, int ldo,
+                    void* solves, ciq_info* info, hipStream_t stream) {
+    return solve_single(p, o, b, s, ldb, out, ldo, solves, info, stream, CIQ_INVSQRT);
+}
+
+int ciq_sqrt_mvm(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb, void* out, int ldo,
+                 void* solves, ciq_info* info, hipStream_t stream) {
+    return solve_single(p, o, b, s, ldb, out, ldo, solves, info, stream, CIQ_SQRT);
+}
+
+int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* const* b, int s,
+                            void* const* out, ciq_info* infos, hipStream_t stream) {
+    if (nprob < 1 || !probs || !o || !b || !out || !infos || nprob > 1024) return CIQ_EINVAL;
+    for (int p = 0; p < nprob; ++p) {
+        const int rc = check_solve_args(&probs[p], o, b[p], s, s, out[p], s, &infos[p]);
+        if (rc != CIQ_OK) return rc;
+        if (probs[p].kernel != probs[0].kernel) return CIQ_EINVAL;
+    }
+    if (o->dtype != CIQ_F32) return CIQ_ENOTSUP;
+    return solve<float>(nprob, probs, o, b, s, s, out, s, nullptr, CIQ_INVSQRT, infos, stream);
+}
+
+int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double* t, const double* w,
+                 const void* solves, const void* g, int s, int ldg, void* db, int lddb, double* dlengthscale,
+                 double* doutputscale, double* dnoise, ciq_info* info, hipStream_t stream) {
+    (void)p; (void)o; (void)mode; (void)t; (void)w; (void)solves; (void)g; (void)s; (void)ldg; (void)db;
+    (void)lddb; (void)dlengthscale; (void)doutputscale; (void)dnoise; (void)info; (void)stream;
+    return CIQ_ENOTSUP;
+}
+
+}  // extern "C"

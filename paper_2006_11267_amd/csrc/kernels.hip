@@ -1,0 +1,851 @@
+// Device kernels of libciq (gfx950).
+//
+//  * Kernel product Y = o^2 k(X, X) V + sigma^2 V without storing K (Sec. 3.2,
+//    Property 1): points are staged through LDS, each lane evaluates the
+//    kernel entries that form its MFMA A-operand directly in registers, and the
+//    tile x V contraction runs on v_mfma_f32_16x16x4_f32 (FP32) with FP32
+//    accumulation. The FP64 path uses plain VALU FMA.
+//  * msMINRES step (Appendix C, Alg. S4): one reduction kernel for the six
+//    FP64 inner products a Lanczos step needs, one single-block FP64 scalar
+//    stage (Lanczos alpha/beta, per-shift Givens QR, stopping rule), and one
+//    fused vector update (next Lanczos vector, per-shift search directions,
+//    quadrature-weighted solution accumulation).
+#include "ciq_internal.h"
+
+#include <cmath>
+
+namespace ciq {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Kernel entry from the squared distance of pre-scaled points.
+//  RBF:      points scaled by sqrt(log2(e)/2)/l  ->  k = 2^{-r2} = exp(-r^2/2)
+//  Matern52: points scaled by sqrt(5)/l          ->  rho = sqrt5 r,
+//            k = (1 + rho + rho^2/3) 2^{-rho log2 e}
+template <int KERNEL>
+__device__ __forceinline__ float kfun32(float r2) {
+    if constexpr (KERNEL == CIQ_KERNEL_RBF) {
+        return __builtin_amdgcn_exp2f(-r2);
+    } else {
+        const float rho = __builtin_amdgcn_sqrtf(r2);
+        const float e = __builtin_amdgcn_exp2f(-kLog2e * rho);
+        return fmaf(rho, fmaf(rho, 1.0f / 3.0f, 1.0f), 1.0f) * e;
+    }
+}
+
+//  RBF:      points scaled by 1/l       ->  k = exp(-r2 / 2)
+//  Matern52: points scaled by sqrt5/l   ->  rho = sqrt(r2), k = (1 + rho + rho^2/3) exp(-rho)
+template <int KERNEL>
+__device__ __forceinline__ double kfun64(double r2) {
+    if constexpr (KERNEL == CIQ_KERNEL_RBF) {
+        return exp(-0.5 * r2);
+    } else {
+        const double rho = sqrt(r2);
+        return (1.0 + rho + rho * rho * (1.0 / 3.0)) * exp(-rho);
+    }
+}
+
+__device__ __forceinline__ int done_now(const int* done) { return done != nullptr && *done != 0; }
+
+// ----------------------------------------------------------------------------
+// FP32 kernel product on MFMA.
+//
+// Work decomposition: a block of 4 waves owns BM = 64*RT consecutive rows of
+// one problem and one of `nsplit` contiguous ranges of columns j of K. Wave w
+// owns rows [16*RT*w, 16*RT*(w+1)) of the block. Per 16 x 16 tile of K and
+// per 16 columns of V, four v_mfma_f32_16x16x4_f32 cover the 16 j's: in step
+// `st` lane l supplies A = K[i0 + l%16][j0 + 4*st + l/16] (computed in
+// registers from its own x_i and the staged x_j) and
+// B = V[j0 + 4*st + l/16][c0 + l%16] (from LDS); the accumulator holds
+// Y[i0 + 4*(l/16) + r][c0 + l%16], r = 0..3.
+// ----------------------------------------------------------------------------
+template <int KERNEL, int DP, int NSB, int RT>
+__global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
+    constexpr int BM = 64 * RT;
+    constexpr int BN = 64;
+    constexpr int S16 = NSB * 16;
+    constexpr int VST = (NSB & 1) ? S16 : S16 + 16;  // LDS row stride: rows j, j+1 hit disjoint banks
+    __shared__ float xs[BN * DP];
+    __shared__ float vs[BN * VST];
+
+    if (done_now(a.done)) return;
+    int n, off, rb;
+    float o2, s2;
+    if (a.wl != nullptr) {
+        const WorkItem wi = a.wl[blockIdx.x];
+        if (a.prob_done != nullptr && a.prob_done[wi.prob]) return;
+        n = a.pn[wi.prob];
+        off = a.poff[wi.prob];
+        rb = wi.rb;
+        o2 = a.po2[wi.prob];
+        s2 = a.ps2[wi.prob];
+    } else {
+        n = a.n;
+        off = 0;
+        rb = blockIdx.x;
+        o2 = (float)a.o2;
+        s2 = (float)a.s2;
+    }
+    const int split = blockIdx.y;
+    const float* __restrict__ xh = static_cast<const float*>(a.xh);
+    const float* __restrict__ v = static_cast<const float*>(a.v);
+    float* __restrict__ y = static_cast<float*>(a.y) + (long long)split * a.ysplit;
+    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int row0 = rb * BM + wave * 16 * RT;
+
+    float xi[RT][DP];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int i = row0 + rt * 16 + (lane & 15);
+#pragma unroll
+        for (int k = 0; k < DP; ++k) xi[rt][k] = (i < n) ? xh[(long long)(off + i) * DP + k] : 0.0f;
+    }
+
+    floatx4 acc[RT][NSB];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int nchunk = (n + BN - 1) / BN;
+    const int c0 = (int)(((long long)split * nchunk) / a.nsplit);
+    const int c1 = (int)(((long long)(split + 1) * nchunk) / a.nsplit);
+
+    for (int c = c0; c < c1; ++c) {
+        const int j0 = c * BN;
+        __syncthreads();
+        for (int e = threadIdx.x; e < BN * DP; e += 256) {
+            const int jj = e / DP;
+            const int j = j0 + jj;
+            xs[e] = (j < n) ? xh[(long long)(off + j0) * DP + e] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < BN * S16; e += 256) {
+            const int jj = e / S16, cc = e - jj * S16;
+            const int j = j0 + jj;
+            vs[jj * VST + cc] = (j < n && cc < s) ? v[(long long)(off + j) * ldv + cc] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jb = 0; jb < BN / 16; ++jb) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int jl = jb * 16 + st * 4 + (lane >> 4);
+                float xj[DP];
+#pragma unroll
+                for (int k = 0; k < DP; ++k) xj[k] = xs[jl * DP + k];
+                float kv[RT];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    float r2 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) {
+                        const float dd = xi[rt][k] - xj[k];
+                        r2 = fmaf(dd, dd, r2);
+                    }
+                    kv[rt] = kfun32<KERNEL>(r2);
+                }
+#pragma unroll
+                for (int sb = 0; sb < NSB; ++sb) {
+                    const float bv = vs[jl * VST + sb * 16 + (lane & 15)];
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[rt], bv, acc[rt][sb], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) {
+            const int cc = sb * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;
+                if (i < n && cc < s) {
+                    float val = o2 * acc[rt][sb][r];
+                    if (split == 0) val = fmaf(s2, v[(long long)(off + i) * ldv + cc], val);
+                    y[(long long)(off + i) * ldy + cc] = val;
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// FP64 kernel product (VALU). Block: 64 rows x 4 j-lanes; grid (row blocks,
+// nsplit, column groups of SC). Each thread accumulates SC columns over its
+// j-lane, the 4 j-lanes are summed in LDS in a fixed order.
+// ----------------------------------------------------------------------------
+template <int KERNEL, int DP, int SC>
+__global__ __launch_bounds__(256) void mvm_f64_kernel(MvmArgs a) {
+    constexpr int BN = 64;
+    __shared__ double xs[BN * DP];
+    __shared__ double vs[BN * SC];
+    __shared__ double red[4 * 64 * SC];
+    if (done_now(a.done)) return;
+    const int n = a.n;
+    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
+    const double* __restrict__ xh = static_cast<const double*>(a.xh);
+    const double* __restrict__ v = static_cast<const double*>(a.v);
+    const int split = blockIdx.y;
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    const int il = threadIdx.x & 63, jl = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + il;
+    const int cg = blockIdx.z * SC;
+    double xi[DP];
+#pragma unroll
+    for (int k = 0; k < DP; ++k) xi[k] = (i < n) ? xh[(long long)i * DP + k] : 0.0;
+    double acc[SC];
+#pragma unroll
+    for (int c = 0; c < SC; ++c) acc[c] = 0.0;
+    const int nchunk = (n + BN - 1) / BN;
+    const int c0 = (int)(((long long)split * nchunk) / a.nsplit);
+    const int c1 = (int)(((long long)(split + 1) * nchunk) / a.nsplit);
+    for (int ch = c0; ch < c1; ++ch) {
+        const int j0 = ch * BN;
+        __syncthreads();
+        for (int e = threadIdx.x; e < BN * DP; e += 256) {
+            const int j = j0 + e / DP;
+            xs[e] = (j < n) ? xh[(long long)j0 * DP + e] : 0.0;
+        }
+        for (int e = threadIdx.x; e < BN * SC; e += 256) {
+            const int jj = e / SC, cc = e - jj * SC;
+            const int j = j0 + jj;
+            vs[e] = (j < n && cg + cc < s) ? v[(long long)j * ldv + cg + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = jl; jj < BN; jj += 4) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DP; ++k) {
+                const double dd = xi[k] - xs[jj * DP + k];
+                r2 = fma(dd, dd, r2);
+            }
+            const double kij = kfun64<KERNEL>(r2);
+#pragma unroll
+            for (int c = 0; c < SC; ++c) acc[c] = fma(kij, vs[jj * SC + c], acc[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < SC; ++c) red[(jl * 64 + il) * SC + c] = acc[c];
+    __syncthreads();
+    if (jl == 0 && i < n) {
+#pragma unroll
+        for (int c = 0; c < SC; ++c) {
+            if (cg + c >= s) break;
+            double val = red[(0 * 64 + il) * SC + c] + red[(1 * 64 + il) * SC + c] +
+                         red[(2 * 64 + il) * SC + c] + red[(3 * 64 + il) * SC + c];
+            val *= a.o2;
+            if (split == 0) val = fma(a.s2, v[(long long)i * ldv + cg + c], val);
+            y[(long long)i * ldy + cg + c] = val;
+        }
+    }
+}
+
+template <int KERNEL, int DP, int NSB>
+hipError_t launch_f32_nsb(const MvmArgs& a, int grid_x, hipStream_t st) {
+    constexpr int RT = (NSB <= 4) ? 2 : 1;
+    dim3 grid(grid_x, a.nsplit);
+    hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, RT>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int KERNEL, int DP>
+hipError_t launch_f32_dp(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
+    switch (nsb) {
+        case 1: return launch_f32_nsb<KERNEL, DP, 1>(a, grid_x, st);
+        case 2: return launch_f32_nsb<KERNEL, DP, 2>(a, grid_x, st);
+        case 3:
+        case 4: return launch_f32_nsb<KERNEL, DP, 4>(a, grid_x, st);
+        case 5: case 6: case 7:
+        case 8: return launch_f32_nsb<KERNEL, DP, 8>(a, grid_x, st);
+        default: return launch_f32_nsb<KERNEL, DP, 16>(a, grid_x, st);
+    }
+}
+
+template <int KERNEL>
+hipError_t launch_f32_k(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
+    switch (a.dp) {
+        case 4: return launch_f32_dp<KERNEL, 4>(a, nsb, grid_x, st);
+        case 8: return launch_f32_dp<KERNEL, 8>(a, nsb, grid_x, st);
+        case 12: return launch_f32_dp<KERNEL, 12>(a, nsb, grid_x, st);
+        default: return launch_f32_dp<KERNEL, 16>(a, nsb, grid_x, st);
+    }
+}
+
+template <int KERNEL, int DP>
+hipError_t launch_f64_dp(const MvmArgs& a, hipStream_t st) {
+    constexpr int SC = 8;
+    dim3 grid((a.n + 63) / 64, a.nsplit, (a.s + SC - 1) / SC);
+    hipLaunchKernelGGL((mvm_f64_kernel<KERNEL, DP, SC>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int KERNEL>
+hipError_t launch_f64_k(const MvmArgs& a, hipStream_t st) {
+    switch (a.dp) {
+        case 4: return launch_f64_dp<KERNEL, 4>(a, st);
+        case 8: return launch_f64_dp<KERNEL, 8>(a, st);
+        case 12: return launch_f64_dp<KERNEL, 12>(a, st);
+        default: return launch_f64_dp<KERNEL, 16>(a, st);
+    }
+}
+
+}  // namespace
+
+int mvm_rows_per_block(int dtype, int s) {
+    if (dtype == CIQ_F64) return 64;
+    const int nsb = (s + 15) / 16;
+    return (nsb <= 4) ? 128 : 64;
+}
+
+// Split the j range so the number of equal-cost blocks fills the chip's
+// resident slots with the least idle tail (blocks per CU assumed ~4).
+int mvm_pick_nsplit(int dtype, int nrb, int n_max) {
+    const int slots = 256 * 4;
+    const int max_split = (dtype == CIQ_F64) ? 16 : 8;
+    int best = 1;
+    double best_eff = 0.0;
+    for (int sp = 1; sp <= max_split; ++sp) {
+        const int chunks = (n_max + 63) / 64;
+        if (sp > chunks) break;
+        const double work = (double)nrb * sp;
+        const double rounds = std::ceil(work / slots);
+        // efficiency of the last round plus a small per-split cost (partials traffic)
+        const double eff = work / (rounds * slots) - 0.02 * (sp - 1);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = sp;
+        }
+    }
+    return best;
+}
+
+hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
+    if (dtype == CIQ_F64) {
+        return a.kernel == CIQ_KERNEL_RBF ? launch_f64_k<CIQ_KERNEL_RBF>(a, st)
+                                          : launch_f64_k<CIQ_KERNEL_MATERN52>(a, st);
+    }
+    // the MFMA kernel holds at most 16 column blocks (256 columns) in
+    // accumulators; wider right-hand sides run as column groups
+    for (int c0 = 0; c0 < a.s; c0 += 256) {
+        MvmArgs g = a;
+        g.s = (a.s - c0 < 256) ? a.s - c0 : 256;
+        g.v = static_cast<const float*>(a.v) + c0;
+        g.y = static_cast<float*>(a.y) + c0;
+        const int nsb = (g.s + 15) / 16;
+        const hipError_t e = a.kernel == CIQ_KERNEL_RBF ? launch_f32_k<CIQ_KERNEL_RBF>(g, nsb, a.nrb, st)
+                                                        : launch_f32_k<CIQ_KERNEL_MATERN52>(g, nsb, a.nrb, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ----------------------------------------------------------------------------
+// Input preparation: xh[i][k] = x[i][k] * scale[k] for k < d, 0 for d <= k < dp.
+// ----------------------------------------------------------------------------
+struct Scale16 {
+    double v[CIQ_MAX_D];
+};
+
+template <typename T>
+__global__ void prep_kernel(const T* x, int n, int d, int dp, Scale16 sc, T* xh) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * dp) return;
+    const int i = (int)(e / dp), k = (int)(e - (long long)i * dp);
+    xh[e] = (k < d) ? (T)((double)x[(long long)i * d + k] * sc.v[k]) : (T)0;
+}
+
+template <typename T>
+hipError_t launch_prep(const T* x, int n, int d, int dp, const double* scale, T* xh, hipStream_t st) {
+    Scale16 sc;
+    for (int k = 0; k < CIQ_MAX_D; ++k) sc.v[k] = (k < d) ? scale[k] : 0.0;
+    const long long total = (long long)n * dp;
+    const int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(prep_kernel<T>, dim3(blocks), dim3(256), 0, st, x, n, d, dp, sc, xh);
+    return hipGetLastError();
+}
+template hipError_t launch_prep<float>(const float*, int, int, int, const double*, float*, hipStream_t);
+template hipError_t launch_prep<double>(const double*, int, int, int, const double*, double*, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Sum of split partials: out[i][c] = sum_k ypart[k][i][c].
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void reduce_splits_kernel(const T* ypart, long long ysplit, int nsplit, int ldy, int n,
+                                     int s, T* out, int ldo) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * s) return;
+    const int i = (int)(e / s), c = (int)(e - (long long)i * s);
+    T acc = ypart[(long long)i * ldy + c];
+    for (int k = 1; k < nsplit; ++k) acc += ypart[k * ysplit + (long long)i * ldy + c];
+    out[(long long)i * ldo + c] = acc;
+}
+
+template <typename T>
+hipError_t launch_reduce_splits(const T* ypart, long long ysplit, int nsplit, int ldy, int n, int s,
+                                T* out, int ldo, hipStream_t st) {
+    const long long total = (long long)n * s;
+    hipLaunchKernelGGL(reduce_splits_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st,
+                       ypart, ysplit, nsplit, ldy, n, s, out, ldo);
+    return hipGetLastError();
+}
+template hipError_t launch_reduce_splits<float>(const float*, long long, int, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_reduce_splits<double>(const double*, long long, int, int, int, int, double*, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Lanczos inner products in two passes (classical orthogonalisation, the
+// order of Appendix C: v = K q_j - beta_j q_{j-1}; alpha_j = q_j^T v;
+// v -= alpha_j q_j; beta_{j+1} = ||v||), FP64 sums of the element products.
+//   phase 0: partial sums of q_j . (Y - beta_j q_{j-1})          -> dots[..][0]
+//   phase 1: alpha_j = sum of the phase-0 partials (fixed order),
+//            partial sums of ||Y - beta_j q_{j-1} - alpha_j q_j||^2 -> dots[..][1]
+//   init (phase 1 with q = q_prev = null): ||b||^2.
+// Y is the sum of the kernel product's split partials. Block: TS columns x RL
+// row lanes; grid (dots_blocks, ceil(s/TS), nprob); row lanes are combined in
+// a fixed order, so the result is deterministic.
+// ----------------------------------------------------------------------------
+__host__ __device__ inline int col_tile(int s) {
+    int ts = 1;
+    while (ts < s && ts < 64) ts <<= 1;
+    return ts;
+}
+
+__device__ inline double sum_partials(const Dev& d, int p, int c, int k) {
+    double acc = 0.0;
+    for (int b = 0; b < d.dots_blocks; ++b) acc += d.dots[(((long long)p * d.dots_blocks + b) * d.s + c) * 2 + k];
+    return acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void dots_kernel(Dev d, const T* y, long long ysplit, int nsplit,
+                                                   const T* q, const T* qp, int phase) {
+    __shared__ double sh[256];
+    __shared__ double s_alpha[64];
+    __shared__ double s_beta[64];
+    if (d.st->done) return;
+    const int TS = col_tile(d.s), RL = 256 / TS;
+    const int p = blockIdx.z;
+    const int n = d.n[p], off = d.row_off[p], s = d.s;
+    const int cl = threadIdx.x % TS, rl = threadIdx.x / TS;
+    const int c = blockIdx.y * TS + cl;
+    if (threadIdx.x < TS) {
+        double al = 0.0, bj = 0.0;
+        if (c < s && q != nullptr) {
+            bj = d.beta_cur[p * s + c];
+            if (phase == 1) al = sum_partials(d, p, c, 0);
+        }
+        s_alpha[threadIdx.x] = al;
+        s_beta[threadIdx.x] = bj;
+    }
+    __syncthreads();
+    const double al = s_alpha[cl], bj = s_beta[cl];
+    double acc = 0.0;
+    if (c < s) {
+        for (int i = blockIdx.x * RL + rl; i < n; i += gridDim.x * RL) {
+            const long long idx = (long long)(off + i) * s + c;
+            double yv = (double)y[idx];
+            for (int k = 1; k < nsplit; ++k) yv += (double)y[k * ysplit + idx];
+            if (q == nullptr) {                       // ||b||^2
+                acc = fma(yv, yv, acc);
+                continue;
+            }
+            // the same arithmetic, in T, as the update kernel forms q_{j+1} with
+            const T vT = (T)yv - (T)bj * qp[idx];
+            if (phase == 0) {
+                acc = fma((double)q[idx], (double)vT, acc);
+            } else {
+                const double v = (double)(vT - (T)al * q[idx]);
+                acc = fma(v, v, acc);
+            }
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < TS && c < s) {
+        double sum = 0.0;
+        for (int r = 0; r < RL; ++r) sum += sh[r * TS + threadIdx.x];
+        d.dots[(((long long)p * d.dots_blocks + blockIdx.x) * s + c) * 2 + (q == nullptr ? 1 : phase)] = sum;
+    }
+}
+
+template <typename T>
+hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q, const T* qp,
+                       int phase, hipStream_t st) {
+    const int TS = col_tile(d.s);
+    dim3 grid(d.dots_blocks, (d.s + TS - 1) / TS, d.nprob);
+    hipLaunchKernelGGL(dots_kernel<T>, grid, dim3(256), 0, st, d, y, ysplit, nsplit, q, qp, phase);
+    return hipGetLastError();
+}
+template hipError_t launch_dots<float>(const Dev&, const float*, long long, int, const float*, const float*, int, hipStream_t);
+template hipError_t launch_dots<double>(const Dev&, const double*, long long, int, const double*, const double*, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Scalar stage (single block, FP64). Initial form: beta_1 = ||b||.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void scalar_init_kernel(Dev d) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int ncol = d.ncol, Q = d.Q;
+    for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
+        const double b1 = sqrt(sum_partials(d, g / d.s, g % d.s, 1));
+        const bool ok = (b1 > 0.0) && isfinite(b1);
+        d.beta1[g] = ok ? b1 : 0.0;
+        d.beta_cur[g] = 0.0;
+        d.inv_beta_next[g] = ok ? 1.0 / b1 : 0.0;
+        d.colactive[g] = ok ? 1 : 0;
+        d.colflag[g] = 0;
+        d.col_iters[g] = 0;
+        if (ok) any = 1;
+        for (int q = 0; q < Q; ++q) {
+            const int idx = q * ncol + g;
+            d.c1[idx] = 1.0; d.s1[idx] = 0.0; d.c2[idx] = 1.0; d.s2[idx] = 0.0;
+            d.phibar[idx] = ok ? b1 : 0.0;
+            d.frozen[idx] = ok ? 0 : 1;
+            d.relres[idx] = ok ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < d.nprob; p += blockDim.x) {
+        int act = 0;
+        for (int c = 0; c < d.s; ++c) act |= d.colactive[p * d.s + c];
+        d.prob_done[p] = act ? 0 : 1;
+    }
+    if (threadIdx.x == 0) {
+        d.st->iter = 0;
+        d.st->live = 0;
+        d.st->numeric = 0;
+        d.st->done = (any && d.max_iter > 0) ? 0 : 1;
+    }
+}
+
+hipError_t launch_scalar_init(const Dev& d, hipStream_t st) {
+    hipLaunchKernelGGL(scalar_init_kernel, dim3(1), dim3(1024), 0, st, d);
+    return hipGetLastError();
+}
+
+// One msMINRES iteration's scalar work (Appendix C.2, per shift t_q):
+//   alpha_j = q_j^T (K q_j - beta_j q_{j-1})
+//   beta_{j+1} = ||K q_j - beta_j q_{j-1} - alpha_j q_j||   (from the two-pass partials)
+//   Givens: eps = s_{j-2} beta_j, dhat = c_{j-2} beta_j,
+//           delta = c_{j-1} dhat + s_{j-1} (alpha_j + t), gbar = -s_{j-1} dhat + c_{j-1} (alpha_j + t),
+//           gamma = hypot(gbar, beta_{j+1}), c = gbar/gamma, s = beta_{j+1}/gamma,
+//           tau = c phibar, phibar <- -s phibar
+// Stopping: shift frozen at |phibar|/||b|| <= tol; column stops when all its
+// shifts are frozen or beta_{j+1} breaks down; run stops at max_iter.
+__global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
+    __shared__ int active_cnt[1024];
+    __shared__ int any;
+    IterState* st = d.st;
+    if (st->done) {
+        if (threadIdx.x == 0) st->live = 0;
+        return;
+    }
+    const int ncol = d.ncol, Q = d.Q, s = d.s;
+    for (int p = threadIdx.x; p < d.nprob; p += blockDim.x) active_cnt[p] = 0;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int iter = st->iter;
+
+    for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
+        if (!d.colactive[g]) continue;
+        const int p = g / s, c = g - p * s;
+        const double bj = d.beta_cur[g];
+        double al = sum_partials(d, p, c, 0);
+        double bn = sqrt(sum_partials(d, p, c, 1));
+        // ||K q_j|| ~ sqrt(alpha^2 + beta_j^2 + beta_{j+1}^2) scales the breakdown test
+        bool broke = !(bn > d.bd_rtol * sqrt(al * al + bj * bj + bn * bn));
+        if (!isfinite(al) || !isfinite(bn)) {
+            st->numeric = 1;
+            broke = true;
+            al = 0.0;
+        }
+        if (d.bounds_mode) {
+            double* tr = d.T + ((long long)iter * ncol + g) * 2;
+            tr[0] = al;
+            tr[1] = bn;
+        }
+        d.alpha[g] = al;
+        d.beta_next[g] = broke ? 0.0 : bn;
+        d.beta_used[g] = bj;
+        d.col_iters[g] += 1;
+    }
+    __syncthreads();
+
+    for (int idx = threadIdx.x; idx < Q * ncol; idx += blockDim.x) {
+        const int g = idx % ncol, q = idx / ncol;
+        ShiftCoef cf;
+        cf.delta = cf.eps = cf.ginv = cf.tau = cf.tauw = 0.0;
+        cf.upd = 0;
+        cf.pad = 0;
+        if (d.colactive[g] && !d.frozen[idx]) {
+            const int p = g / s;
+            const double a = d.alpha[g] + d.t[p * Q + q];
+            const double bj = d.beta_used[g], bn = d.beta_next[g];
+            const double c1 = d.c1[idx], s1 = d.s1[idx], c2 = d.c2[idx], s2 = d.s2[idx];
+            const double eps = s2 * bj;
+            const double dhat = c2 * bj;
+            const double delta = c1 * dhat + s1 * a;
+            const double gbar = -s1 * dhat + c1 * a;
+            const double gamma = hypot(gbar, bn);
+            double cn = 1.0, sn = 0.0, ginv = 0.0;
+            if (gamma > 0.0 && isfinite(gamma)) {
+                cn = gbar / gamma;
+                sn = bn / gamma;
+                ginv = 1.0 / gamma;
+            } else {
+                st->numeric = 1;
+            }
+            const double ph = d.phibar[idx];
+            const double tau = cn * ph;
+            const double phn = -sn * ph;
+            cf.delta = delta;
+            cf.eps = eps;
+            cf.ginv = ginv;
+            cf.tau = tau;
+            cf.tauw = d.w[p * Q + q] * tau;
+            cf.upd = 1;
+            d.c2[idx] = c1; d.s2[idx] = s1; d.c1[idx] = cn; d.s1[idx] = sn;
+            d.phibar[idx] = phn;
+            const double rr = fabs(phn) / d.beta1[g];
+            d.relres[idx] = rr;
+            if (rr <= d.tol) d.frozen[idx] = 1;
+        }
+        d.coef[idx] = cf;
+    }
+    __syncthreads();
+
+    for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
+        if (!d.colactive[g]) {
+            d.colflag[g] = 0;
+            continue;
+        }
+        const bool broke = (d.beta_next[g] == 0.0);
+        bool all_frozen = (Q > 0);
+        for (int q = 0; q < Q; ++q) all_frozen = all_frozen && d.frozen[q * ncol + g];
+        const bool cont = !(broke || all_frozen);
+        d.colflag[g] = cont ? 2 : 1;
+        d.inv_beta_next[g] = cont ? 1.0 / d.beta_next[g] : 0.0;
+        if (cont) {
+            d.beta_cur[g] = d.beta_next[g];
+            atomicAdd(&active_cnt[g / s], 1);
+            any = 1;
+        } else {
+            d.colactive[g] = 0;
+            for (int q = 0; q < Q; ++q) d.frozen[q * ncol + g] = 1;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < d.nprob; p += blockDim.x) d.prob_done[p] = active_cnt[p] ? 0 : 1;
+    if (threadIdx.x == 0) {
+        st->iter = iter + 1;
+        st->live = 1;
+        if (!any || iter + 1 >= d.max_iter) st->done = 1;
+    }
+}
+
+hipError_t launch_scalar(const Dev& d, hipStream_t st) {
+    hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(1024), 0, st, d);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Fused vector update of one msMINRES iteration (column g, row i):
+//   per unfrozen shift q: m_j = (q_j - delta m_{j-1} - eps m_{j-2}) * ginv,
+//                          acc += w_q tau m_j,  x^{(q)} += tau m_j  (if kept)
+//   if the column continues: q_{j+1} = (K q_j - beta_j q_{j-1} - alpha_j q_j) / beta_{j+1}
+// m_j overwrites m_{j-2}; q_{j+1} overwrites q_{j-1}.
+// Block: TS columns x RL row lanes; grid (blocks, ceil(s/TS), nprob).
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long long ysplit, int nsplit,
+                                                     const T* qcur, T* qprev, const T* m_prev,
+                                                     T* m_cur, T* acc, T* solves, long long mstride,
+                                                     int TS) {
+    extern __shared__ char smem[];
+    if (!d.st->live) return;
+    const int RL = 256 / TS;
+    const int Q = d.Q, s = d.s, ncol = d.ncol;
+    T* sdelta = reinterpret_cast<T*>(smem);
+    T* seps = sdelta + Q * TS;
+    T* sginv = seps + Q * TS;
+    T* stau = sginv + Q * TS;
+    T* stauw = stau + Q * TS;
+    int* supd = reinterpret_cast<int*>(stauw + Q * TS);
+    const int p = blockIdx.z;
+    const int cbase = blockIdx.y * TS;
+    for (int e = threadIdx.x; e < Q * TS; e += blockDim.x) {
+        const int q = e / TS, cc = e % TS;
+        const int c = cbase + cc;
+        ShiftCoef cf;
+        if (c < s) {
+            cf = d.coef[q * ncol + p * s + c];
+        } else {
+            cf.delta = cf.eps = cf.ginv = cf.tau = cf.tauw = 0.0;
+            cf.upd = 0;
+        }
+        sdelta[e] = (T)cf.delta; seps[e] = (T)cf.eps; sginv[e] = (T)cf.ginv;
+        stau[e] = (T)cf.tau; stauw[e] = (T)cf.tauw; supd[e] = cf.upd;
+    }
+    __syncthreads();
+    const int cl = threadIdx.x % TS, rl = threadIdx.x / TS;
+    const int c = cbase + cl;
+    if (c >= s) return;
+    const int g = p * s + c;
+    const int flag = d.colflag[g];
+    if (flag == 0) return;
+    const int n = d.n[p], off = d.row_off[p];
+    const T al = (T)d.alpha[g];
+    const T bj = (T)d.beta_used[g];
+    const T ib = (T)d.inv_beta_next[g];
+    for (int i = blockIdx.x * RL + rl; i < n; i += gridDim.x * RL) {
+        const long long row = off + i;
+        const long long idx = row * s + c;
+        const T qj = qcur[idx];
+        T a = (T)0;
+        for (int q = 0; q < Q; ++q) {
+            const int e = q * TS + cl;
+            if (!supd[e]) continue;
+            const long long midx = q * mstride + idx;
+            const T m = (qj - sdelta[e] * m_prev[midx] - seps[e] * m_cur[midx]) * sginv[e];
+            m_cur[midx] = m;
+            a += stauw[e] * m;
+            if (solves) solves[(row * Q + q) * s + c] += stau[e] * m;
+        }
+        acc[idx] += a;
+        if (flag == 2) {
+            double ys = (double)y[idx];
+            for (int k = 1; k < nsplit; ++k) ys += (double)y[k * ysplit + idx];
+            const T vT = (T)ys - bj * qprev[idx];     // same arithmetic as the inner products
+            const T v = vT - al * qj;
+            qprev[idx] = v * ib;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur, T* qprev,
+                         const T* m_prev, T* m_cur, T* acc, T* solves, int max_n, hipStream_t st) {
+    const size_t per = 5 * sizeof(T) + sizeof(int);   // LDS bytes per (shift, column)
+    int TS = col_tile(d.s);
+    while (TS > 1 && (size_t)d.Q * TS * per > 49152) TS >>= 1;   // coefficient tile <= 48 KB LDS
+    const int RL = 256 / TS;
+    int bx = (max_n + RL - 1) / RL;
+    if (bx > 512) bx = 512;
+    if (bx < 1) bx = 1;
+    dim3 grid(bx, (d.s + TS - 1) / TS, d.nprob);
+    const size_t shm = (size_t)d.Q * TS * per;
+    const long long mstride = (long long)d.rows_total * d.s;
+    hipLaunchKernelGGL(update_kernel<T>, grid, dim3(256), shm, st, d, y, ysplit, nsplit, qcur, qprev,
+                       m_prev, m_cur, acc, solves, mstride, TS);
+    return hipGetLastError();
+}
+template hipError_t launch_update<float>(const Dev&, const float*, long long, int, const float*, float*,
+                                         const float*, float*, float*, float*, int, hipStream_t);
+template hipError_t launch_update<double>(const Dev&, const double*, long long, int, const double*, double*,
+                                          const double*, double*, double*, double*, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Start of a run: q_1 = b / ||b|| (0 for a zero column), q_0 = 0, acc = 0.
+// The caller has copied B into q and zeroed the direction/solve buffers.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)d.rows_total * d.s;
+    if (e >= total) return;
+    const int row = (int)(e / d.s), c = (int)(e - (long long)row * d.s);
+    int p = 0;
+    while (p + 1 < d.nprob && d.row_off[p + 1] <= row) ++p;
+    const T inv = (T)d.inv_beta_next[p * d.s + c];
+    q[e] = q[e] * inv;
+    qprev[e] = (T)0;
+    acc[e] = (T)0;
+}
+
+template <typename T>
+hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, int rows, hipStream_t st) {
+    const long long total = (long long)rows * d.s;
+    hipLaunchKernelGGL(init_vectors_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, d, q,
+                       qprev, acc);
+    return hipGetLastError();
+}
+template hipError_t launch_init_vectors<float>(const Dev&, float*, float*, float*, int, hipStream_t);
+template hipError_t launch_init_vectors<double>(const Dev&, double*, double*, double*, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Strided copy, fill, counter-based random start vector.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void copy2d_kernel(const T* src, int ld_src, int n, int s, T* dst, int ld_dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * s) return;
+    const int i = (int)(e / s), c = (int)(e - (long long)i * s);
+    dst[(long long)i * ld_dst + c] = src[(long long)i * ld_src + c];
+}
+
+template <typename T>
+hipError_t launch_copy_in(const T* src, int ld_src, int n, int s, T* dst, int ld_dst, hipStream_t st) {
+    const long long total = (long long)n * s;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy2d_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, src, ld_src,
+                       n, s, dst, ld_dst);
+    return hipGetLastError();
+}
+template hipError_t launch_copy_in<float>(const float*, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_copy_in<double>(const double*, int, int, int, double*, int, hipStream_t);
+
+template <typename T>
+__global__ void fill_kernel(T* p, size_t count, T value) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = value;
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t count, T value, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count,
+                       value);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<float>(float*, size_t, float, hipStream_t);
+template hipError_t launch_fill<double>(double*, size_t, double, hipStream_t);
+template hipError_t launch_fill<int>(int*, size_t, int, hipStream_t);
+
+// SplitMix64 (Steele, Lea, Flood 2014) evaluated at counter i: a uniform
+// draw on [-1, 1) per entry, independent of the launch shape.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void splitmix_kernel(T* v, int n, uint64_t seed, int ld) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t z = splitmix64(seed + 0x9E3779B97F4A7C15ull * (uint64_t)i);
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    v[(long long)i * ld] = (T)(2.0 * u - 1.0);
+}
+
+template <typename T>
+hipError_t launch_splitmix(T* v, int n, uint64_t seed, int ld, hipStream_t st) {
+    hipLaunchKernelGGL(splitmix_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, v, n, seed, ld);
+    return hipGetLastError();
+}
+template hipError_t launch_splitmix<float>(float*, int, uint64_t, int, hipStream_t);
+template hipError_t launch_splitmix<double>(double*, int, uint64_t, int, hipStream_t);
+
+}  // namespace ciq

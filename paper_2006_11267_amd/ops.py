@@ -1,0 +1,171 @@
+"""Python entry points with the C ABI's names (include/ciq.h), taking torch
+tensors for device memory and torch's current stream. Marshalling only."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor, precision: Optional[str]) -> int:
+    if precision is not None:
+        return L.DTYPES[precision]
+    if t.dtype == torch.float64:
+        return L.CIQ_F64
+    if t.dtype == torch.float32:
+        return L.CIQ_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _elem_dtype(code: int) -> torch.dtype:
+    return torch.float64 if code == L.CIQ_F64 else torch.float32
+
+
+@dataclass
+class Problem:
+    """K = outputscale * k(X, X) + noise * I with X a device tensor (n x d)."""
+
+    x: torch.Tensor
+    kernel: str = "rbf"
+    lengthscale: Sequence[float] = (1.0,)
+    outputscale: float = 1.0
+    noise: float = 0.0
+
+    def c_struct(self):
+        x = self.x
+        if not (x.is_cuda and x.dim() == 2 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous 2-D device tensor")
+        ls = np.ascontiguousarray(np.asarray(self.lengthscale, dtype=np.float64).reshape(-1))
+        arr = (ctypes.c_double * ls.size)(*ls.tolist())
+        p = L.ciq_problem(
+            n=x.shape[0], d=x.shape[1], x=ctypes.c_void_p(x.data_ptr()), kernel=L.KERNELS[self.kernel],
+            n_lengthscale=ls.size, lengthscale=ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)),
+            outputscale=float(self.outputscale), noise=float(self.noise))
+        return p, arr  # keep arr alive with p
+
+
+def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, check_every=0, profile=False):
+    o = L.ciq_opts()
+    o.dtype = dtype_code
+    o.q = int(q)
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.lanczos_steps = int(lanczos_steps)
+    o.seed = int(seed)
+    if bounds is not None:
+        o.lambda_min, o.lambda_max = float(bounds[0]), float(bounds[1])
+    o.check_every = int(check_every)
+    o.profile = 1 if profile else 0
+    return o
+
+
+def ciq_version() -> int:
+    return L.load().ciq_version()
+
+
+def ciq_setup(lambda_min: float, lambda_max: float, q: int):
+    """HHT shifts t (ascending) and weights w (host FP64)."""
+    lib = L.load()
+    t = (ctypes.c_double * q)()
+    w = (ctypes.c_double * q)()
+    L.check(lib.ciq_setup(float(lambda_min), float(lambda_max), int(q), t, w), "ciq_setup")
+    return np.array(t[:]), np.array(w[:])
+
+
+def ciq_kernel_mvm(problem: Problem, v: torch.Tensor, precision: Optional[str] = None) -> torch.Tensor:
+    """Y = K V (on the current stream, asynchronous)."""
+    lib = L.load()
+    code = _dtype_code(problem.x, precision)
+    v2 = v if v.dim() == 2 else v.reshape(-1, 1)
+    y = torch.empty(v2.shape, dtype=_elem_dtype(code), device=v.device)
+    p, keep = problem.c_struct()
+    L.check(lib.ciq_kernel_mvm(ctypes.byref(p), code, ctypes.c_void_p(v2.data_ptr()), v2.shape[1],
+                               v2.stride(0), ctypes.c_void_p(y.data_ptr()), y.stride(0), _stream()),
+            "ciq_kernel_mvm")
+    del keep
+    return y.reshape(v.shape)
+
+
+def ciq_eig_bounds(problem: Problem, steps: int = 20, v0: Optional[torch.Tensor] = None, seed: int = 0,
+                   precision: Optional[str] = None):
+    lib = L.load()
+    code = _dtype_code(problem.x, precision)
+    p, keep = problem.c_struct()
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    vp = ctypes.c_void_p(v0.data_ptr()) if v0 is not None else None
+    L.check(lib.ciq_eig_bounds(ctypes.byref(p), code, int(steps), vp, int(seed), ctypes.byref(lo),
+                               ctypes.byref(hi), _stream()), "ciq_eig_bounds")
+    del keep
+    return lo.value, hi.value
+
+
+def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves, lanczos_steps, seed,
+           check_every, profile):
+    lib = L.load()
+    code = _dtype_code(problem.x, precision)
+    b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+    if b2.stride(1) != 1:
+        b2 = b2.contiguous()
+    n, s = b2.shape
+    out = torch.empty((n, s), dtype=_elem_dtype(code), device=b.device)
+    solves = torch.empty((n, q, s), dtype=_elem_dtype(code), device=b.device) if keep_solves else None
+    p, keep = problem.c_struct()
+    o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile)
+    info = L.ciq_info()
+    fn = getattr(lib, fn_name)
+    L.check(fn(ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s, b2.stride(0),
+               ctypes.c_void_p(out.data_ptr()), out.stride(0),
+               ctypes.c_void_p(solves.data_ptr()) if solves is not None else None, ctypes.byref(info), _stream()),
+            fn_name)
+    del keep
+    return out.reshape(b.shape), info.as_dict(), solves
+
+
+def ciq_invsqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
+                    precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
+                    lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False):
+    """K^{-1/2} B -> (out, info, solves or None)."""
+    return _solve("ciq_invsqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
+                  lanczos_steps, seed, check_every, profile)
+
+
+def ciq_sqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
+                 precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
+                 lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False):
+    """K^{1/2} B -> (out, info, solves or None)."""
+    return _solve("ciq_sqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
+                  lanczos_steps, seed, check_every, profile)
+
+
+def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tensor], q: int = 12,
+                            max_iter: int = 1000, tol: float = 1e-4, bounds=None, lanczos_steps: int = 0,
+                            seed: int = 0, check_every: int = 0, profile: bool = False):
+    """[K_p^{-1/2} B_p] for independent problems in one run -> (outs, infos)."""
+    lib = L.load()
+    P = len(problems)
+    s = bs[0].shape[1]
+    structs, keeps = [], []
+    for pr in problems:
+        c, k = pr.c_struct()
+        structs.append(c)
+        keeps.append(k)
+    parr = (L.ciq_problem * P)(*structs)
+    bcont = [b.contiguous() for b in bs]
+    outs = [torch.empty_like(b) for b in bcont]
+    bp = (ctypes.c_void_p * P)(*[b.data_ptr() for b in bcont])
+    op = (ctypes.c_void_p * P)(*[o.data_ptr() for o in outs])
+    infos = (L.ciq_info * P)()
+    o = _opts(L.CIQ_F32, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile)
+    L.check(lib.ciq_invsqrt_mvm_batched(P, parr, ctypes.byref(o), bp, s, op, infos, _stream()),
+            "ciq_invsqrt_mvm_batched")
+    del keeps
+    return outs, [i.as_dict() for i in infos]
