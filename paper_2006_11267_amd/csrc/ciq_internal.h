@@ -74,8 +74,8 @@ struct WorkItem {
 // Arguments of one kernel-product launch Y = K V (split over the j range).
 struct MvmArgs {
     const void* xh;          // scaled, zero-padded points: rows x dp
-    const void* v;           // rows x s (ld = ldv)
-    void* y;                 // partial outputs: nsplit x rows x s (ld = ldy)
+    const void* v;           // rows x s (ld = ldv); float (FP32 path) or double
+    void* y;                 // double partial outputs: nsplit x rows x s (ld = ldy)
     long long ysplit;        // elements between split partials
     int ldv, ldy;
     int s;
@@ -98,16 +98,17 @@ struct MvmArgs {
 
 // ---- launchers (kernels.hip) ------------------------------------------------
 int mvm_rows_per_block(int dtype, int s);
-int mvm_pick_nsplit(int dtype, int nrb, int n_max);
+int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s);
 hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st);
 
 template <typename T>
 hipError_t launch_prep(const T* x, int n, int d, int dp, const double* scale, T* xh,
                        hipStream_t st);
 
-template <typename T>
-hipError_t launch_reduce_splits(const T* ypart, long long ysplit, int nsplit, int ldy,
-                                int n, int s, T* out, int ldo, hipStream_t st);
+// ypart: double partials of the kernel product (both paths accumulate in FP64)
+template <typename TO>
+hipError_t launch_reduce_splits(const double* ypart, long long ysplit, int nsplit, int ldy,
+                                int n, int s, TO* out, int ldo, hipStream_t st);
 
 template <typename T>
 hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q,
@@ -116,17 +117,19 @@ hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, c
 hipError_t launch_scalar_init(const Dev& d, hipStream_t st);
 hipError_t launch_scalar(const Dev& d, hipStream_t st);
 
+// q32 (nullable): FP32 copy of the next Lanczos vector, the FP32 product's operand
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur,
-                         T* qprev, const T* m_prev, T* m_cur, T* acc, T* solves, int max_n,
-                         hipStream_t st);
+                         T* qprev, const T* m_prev, T* m_cur, T* acc, T* solves, float* q32,
+                         int max_n, hipStream_t st);
 
 template <typename T>
-hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, int rows, hipStream_t st);
+hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows,
+                               hipStream_t st);
 
-template <typename T>
-hipError_t launch_copy_in(const T* src, int ld_src, int n, int s, T* dst, int ld_dst,
-                          hipStream_t st);
+template <typename TI, typename TO>
+hipError_t launch_copy(const TI* src, int ld_src, int n, int s, TO* dst, int ld_dst,
+                       hipStream_t st);
 
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, T value, hipStream_t st);

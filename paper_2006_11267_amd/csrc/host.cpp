@@ -154,13 +154,16 @@ struct Run {
     int bounds_mode = 0;
     int nsplit = 1, nrb = 0;
     bool keep_solves = false;
-    // device memory
+    // device memory: points in the I/O type T, every msMINRES vector in FP64
+    // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
+    // consumes an FP32 copy q32 of the current Lanczos vector)
     T* xh = nullptr;
-    T* qbuf[2] = {nullptr, nullptr};
-    T* ypart = nullptr;
-    T* mbuf[2] = {nullptr, nullptr};
-    T* acc = nullptr;
-    T* solves = nullptr;  // [rows][Q][s]
+    double* qbuf[2] = {nullptr, nullptr};
+    double* ypart = nullptr;
+    double* mbuf[2] = {nullptr, nullptr};
+    double* acc = nullptr;
+    double* solves = nullptr;  // [rows][Q][s]
+    float* q32 = nullptr;      // FP32 product operand (T = float only)
     WorkItem* wl = nullptr;
     int* pn = nullptr;
     int* poff = nullptr;
@@ -180,15 +183,16 @@ struct Run {
         const int ncol = nprob * s;
         const size_t vec = (size_t)rows_total * s;
         if (with_xh) xh = a.template take<T>((size_t)rows_total * dp);
-        qbuf[0] = a.template take<T>(vec);
-        qbuf[1] = a.template take<T>(vec);
-        ypart = a.template take<T>(vec * nsplit);
+        qbuf[0] = a.template take<double>(vec);
+        qbuf[1] = a.template take<double>(vec);
+        ypart = a.template take<double>(vec * nsplit);
         if (Q > 0) {
-            mbuf[0] = a.template take<T>(vec * Q);
-            mbuf[1] = a.template take<T>(vec * Q);
+            mbuf[0] = a.template take<double>(vec * Q);
+            mbuf[1] = a.template take<double>(vec * Q);
         }
-        acc = a.template take<T>(vec);
-        if (keep_solves) solves = a.template take<T>(vec * Q);
+        acc = a.template take<double>(vec);
+        if (keep_solves) solves = a.template take<double>(vec * Q);
+        if (sizeof(T) == 4) q32 = a.template take<float>(vec);
         wl = a.template take<WorkItem>(std::max(nrb, 1));
         pn = a.template take<int>(nprob);
         poff = a.template take<int>(nprob);
@@ -226,7 +230,7 @@ struct Run {
         d.dots_blocks = std::min(64, std::max(1, (max_n + 255) / 256));
         nrb = 0;
         for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rows_per_block - 1) / rows_per_block;
-        nsplit = mvm_pick_nsplit(dtype, nrb, max_n);
+        nsplit = mvm_pick_nsplit(dtype, nrb, max_n, s);
         ysplit = (long long)rows_total * s;
     }
 
@@ -261,7 +265,7 @@ struct Run {
         return CIQ_OK;
     }
 
-    MvmArgs mvm_args(const T* v, T* y) const {
+    MvmArgs mvm_args(const void* v, double* y) const {
         MvmArgs a{};
         a.xh = xh;
         a.v = v;
@@ -290,32 +294,35 @@ struct Run {
     // Krylov iterations after the start vectors are in qbuf[0]. Returns status.
     int iterate(hipStream_t st, int check_every, IterState* pinned, int* mvm_count,
                 hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed) {
-        HIPCHK(launch_dots<T>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
+        // the state is reused scratch: clear `done` before the first kernel that reads it
+        HIPCHK(launch_fill<int>(reinterpret_cast<int*>(d.st), sizeof(IterState) / sizeof(int), 0, st));
+        HIPCHK(launch_dots<double>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
         HIPCHK(launch_scalar_init(d, st));
         if (Q > 0) {
-            HIPCHK(launch_fill<T>(mbuf[0], (size_t)rows_total * s * Q, (T)0, st));
-            HIPCHK(launch_fill<T>(mbuf[1], (size_t)rows_total * s * Q, (T)0, st));
+            HIPCHK(launch_fill<double>(mbuf[0], (size_t)rows_total * s * Q, 0.0, st));
+            HIPCHK(launch_fill<double>(mbuf[1], (size_t)rows_total * s * Q, 0.0, st));
         }
-        if (solves) HIPCHK(launch_fill<T>(solves, (size_t)rows_total * s * Q, (T)0, st));
-        HIPCHK(launch_init_vectors<T>(d, qbuf[0], qbuf[1], acc, rows_total, st));
+        if (solves) HIPCHK(launch_fill<double>(solves, (size_t)rows_total * s * Q, 0.0, st));
+        HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st));
         int j = 1;
         int pending = 0;
         while (j <= max_iter) {
-            T* qcur = qbuf[(j - 1) & 1];
-            T* qprv = qbuf[j & 1];
-            T* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
-            T* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
+            double* qcur = qbuf[(j - 1) & 1];
+            double* qprv = qbuf[j & 1];
+            double* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
+            double* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
             const bool timed = ev_pool != nullptr && pending < n_ev;
             if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
-            HIPCHK(launch_mvm(dtype, mvm_args(qcur, ypart), st));
+            HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qcur, ypart), st));
             if (timed) {
                 HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
                 ++pending;
             }
-            HIPCHK(launch_dots<T>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
-            HIPCHK(launch_dots<T>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+            HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+            HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
             HIPCHK(launch_scalar(d, st));
-            HIPCHK(launch_update<T>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, max_n, st));
+            HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, q32,
+                                         max_n, st));
             if (j % check_every == 0 || j == max_iter) {
                 HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
@@ -475,7 +482,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     } else {
         STCHK(bnd.upload_tables(st, rpb_b));
         for (int p = 0; p < nprob; ++p)
-            HIPCHK(launch_splitmix<T>(bnd.qbuf[0] + bnd.h_off[p], bnd.h_n[p], o->seed + 7919ull * p, 1, st));
+            HIPCHK(launch_splitmix<double>(bnd.qbuf[0] + bnd.h_off[p], bnd.h_n[p], o->seed + 7919ull * p, 1, st));
         int cnt = 0, dummy_n = 0;
         double dummy = 0.0;
         STCHK(bnd.iterate(st, std::max(steps, 1), pinned, &cnt, nullptr, 0, &dummy, &dummy_n));
@@ -512,8 +519,8 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
 
     // ---- right-hand sides --------------------------------------------------
     for (int p = 0; p < nprob; ++p)
-        HIPCHK(launch_copy_in<T>(static_cast<const T*>(b_ptrs[p]), ldb, main.h_n[p], s,
-                                 main.qbuf[0] + (size_t)main.h_off[p] * s, s, st));
+        HIPCHK((launch_copy<T, double>(static_cast<const T*>(b_ptrs[p]), ldb, main.h_n[p], s,
+                                       main.qbuf[0] + (size_t)main.h_off[p] * s, s, st)));
     HIPCHK(hipStreamSynchronize(st));  // th/wh are pageable host vectors
 
     STCHK(main.iterate(st, check_every, pinned, &mvm_count, profile ? evs.data() : nullptr,
@@ -522,24 +529,27 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
 
     // ---- combine -----------------------------------------------------------
     if (mode == CIQ_SQRT) {
-        HIPCHK(launch_mvm(dtype, [&] {
-            MvmArgs a = main.mvm_args(main.acc, main.ypart);
-            a.done = nullptr;
-            a.prob_done = nullptr;
-            return a;
-        }(), st));
+        const void* operand = main.acc;
+        if (main.q32) {
+            HIPCHK((launch_copy<double, float>(main.acc, s, main.rows_total, s, main.q32, s, st)));
+            operand = main.q32;
+        }
+        MvmArgs a = main.mvm_args(operand, main.ypart);
+        a.done = nullptr;
+        a.prob_done = nullptr;
+        HIPCHK(launch_mvm(dtype, a, st));
         mvm_count += 1;
         for (int p = 0; p < nprob; ++p)
             HIPCHK(launch_reduce_splits<T>(main.ypart + (size_t)main.h_off[p] * s, main.ysplit, main.nsplit, s,
                                            main.h_n[p], s, static_cast<T*>(out_ptrs[p]), ldo, st));
     } else {
         for (int p = 0; p < nprob; ++p)
-            HIPCHK(launch_copy_in<T>(main.acc + (size_t)main.h_off[p] * s, s, main.h_n[p], s,
-                                     static_cast<T*>(out_ptrs[p]), ldo, st));
+            HIPCHK((launch_copy<double, T>(main.acc + (size_t)main.h_off[p] * s, s, main.h_n[p], s,
+                                           static_cast<T*>(out_ptrs[p]), ldo, st)));
     }
     if (solves_out) {
-        HIPCHK(hipMemcpyAsync(solves_out, main.solves, (size_t)main.rows_total * main.Q * s * sizeof(T),
-                              hipMemcpyDeviceToDevice, st));
+        HIPCHK((launch_copy<double, T>(main.solves, s, main.rows_total * main.Q, s, static_cast<T*>(solves_out),
+                                       s, st)));
     }
 
     // ---- report ------------------------------------------------------------
@@ -630,10 +640,12 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     const size_t esz = (dtype == CIQ_F64) ? 8 : 4;
     const int rpb = mvm_rows_per_block(dtype, s);
     const int nrb = (p->n + rpb - 1) / rpb;
-    const int nsplit = mvm_pick_nsplit(dtype, nrb, p->n);
-    // stream-ordered scratch: scaled points (+ split partials when nsplit > 1)
+    const int nsplit = mvm_pick_nsplit(dtype, nrb, p->n, s);
+    // stream-ordered scratch: scaled points + FP64 split partials (the FP32
+    // product accumulates in FP64; the last step rounds to the caller's type)
     const size_t xbytes = ((size_t)p->n * dp * esz + 255) & ~size_t(255);
-    const size_t ybytes = (nsplit > 1) ? (size_t)nsplit * p->n * s * esz : 0;
+    const bool direct = (dtype == CIQ_F64 && nsplit == 1);
+    const size_t ybytes = direct ? 0 : (size_t)nsplit * p->n * s * sizeof(double);
     void* buf = nullptr;
     if (hipMallocAsync(&buf, xbytes + ybytes, stream) != hipSuccess) {
         (void)hipGetLastError();
@@ -652,10 +664,10 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     MvmArgs a{};
     a.xh = buf;
     a.v = v;
-    a.y = (nsplit > 1) ? static_cast<void*>(static_cast<char*>(buf) + xbytes) : y;
-    a.ysplit = (nsplit > 1) ? (long long)p->n * s : 0;
+    a.y = direct ? y : static_cast<void*>(static_cast<char*>(buf) + xbytes);
+    a.ysplit = direct ? 0 : (long long)p->n * s;
     a.ldv = ldv;
-    a.ldy = (nsplit > 1) ? s : ldy;
+    a.ldy = direct ? ldy : s;
     a.s = s;
     a.kernel = p->kernel;
     a.dp = dp;
@@ -665,12 +677,12 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     a.s2 = p->noise;
     a.nrb = nrb;
     if (launch_mvm(dtype, a, stream) != hipSuccess) return CIQ_EHIP;
-    if (nsplit > 1) {
+    if (!direct) {
         if (dtype == CIQ_F64)
             e = launch_reduce_splits<double>(static_cast<const double*>(a.y), a.ysplit, nsplit, s, p->n, s,
                                              static_cast<double*>(y), ldy, stream);
         else
-            e = launch_reduce_splits<float>(static_cast<const float*>(a.y), a.ysplit, nsplit, s, p->n, s,
+            e = launch_reduce_splits<float>(static_cast<const double*>(a.y), a.ysplit, nsplit, s, p->n, s,
                                             static_cast<float*>(y), ldy, stream);
         if (e != hipSuccess) return CIQ_EHIP;
     }
@@ -707,9 +719,9 @@ int ciq_eig_bounds(const ciq_problem* p, int dtype, int steps, const void* v0, u
         STCHK(r.upload_tables(stream, rpb));
         STCHK(setup_points(r, p, dtype, stream));
         if (v0)
-            HIPCHK(launch_copy_in<T>(static_cast<const T*>(v0), 1, p->n, 1, r.qbuf[0], 1, stream));
+            HIPCHK((launch_copy<T, double>(static_cast<const T*>(v0), 1, p->n, 1, r.qbuf[0], 1, stream)));
         else
-            HIPCHK(launch_splitmix<T>(r.qbuf[0], p->n, seed, 1, stream));
+            HIPCHK(launch_splitmix<double>(r.qbuf[0], p->n, seed, 1, stream));
         int cnt = 0, dummy_n = 0;
         double dummy = 0.0;
         IterState* pinned = g_scratch[dev].pinned;

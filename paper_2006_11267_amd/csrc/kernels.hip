@@ -62,6 +62,13 @@ __device__ __forceinline__ int done_now(const int* done) { return done != nullpt
 // registers from its own x_i and the staged x_j) and
 // B = V[j0 + 4*st + l/16][c0 + l%16] (from LDS); the accumulator holds
 // Y[i0 + 4*(l/16) + r][c0 + l%16], r = 0..3.
+//
+// Accumulation: the MFMA accumulates one staged chunk of BN columns of K in
+// FP32; each lane then adds its chunk sums into FP64 registers and restarts
+// the FP32 accumulator. A plain FP32 accumulation over all N/nsplit columns
+// loses ~sqrt(N) eps32 per output, and CIQ amplifies product errors by up to
+// kappa(K); with the FP64 running sums the products carry only the rounding
+// of the FP32 kernel entries and of short FP32 chunk sums.
 // ----------------------------------------------------------------------------
 template <int KERNEL, int DP, int NSB, int RT>
 __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
@@ -74,7 +81,7 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
 
     if (done_now(a.done)) return;
     int n, off, rb;
-    float o2, s2;
+    double o2, s2;
     if (a.wl != nullptr) {
         const WorkItem wi = a.wl[blockIdx.x];
         if (a.prob_done != nullptr && a.prob_done[wi.prob]) return;
@@ -87,13 +94,13 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
         n = a.n;
         off = 0;
         rb = blockIdx.x;
-        o2 = (float)a.o2;
-        s2 = (float)a.s2;
+        o2 = a.o2;
+        s2 = a.s2;
     }
     const int split = blockIdx.y;
     const float* __restrict__ xh = static_cast<const float*>(a.xh);
     const float* __restrict__ v = static_cast<const float*>(a.v);
-    float* __restrict__ y = static_cast<float*>(a.y) + (long long)split * a.ysplit;
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
     const int s = a.s, ldv = a.ldv, ldy = a.ldy;
 
     const int lane = threadIdx.x & 63;
@@ -109,10 +116,15 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     }
 
     floatx4 acc[RT][NSB];
+    double accd[RT][NSB][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int sb = 0; sb < NSB; ++sb) acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int sb = 0; sb < NSB; ++sb) {
+            acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
+        }
 
     const int nchunk = (n + BN - 1) / BN;
     const int c0 = (int)(((long long)split * nchunk) / a.nsplit);
@@ -160,6 +172,14 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
                 }
             }
         }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[rt][sb][r];
+                acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
     }
 
 #pragma unroll
@@ -171,8 +191,8 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
             for (int r = 0; r < 4; ++r) {
                 const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;
                 if (i < n && cc < s) {
-                    float val = o2 * acc[rt][sb][r];
-                    if (split == 0) val = fmaf(s2, v[(long long)(off + i) * ldv + cc], val);
+                    double val = (double)o2 * accd[rt][sb][r];
+                    if (split == 0) val = fma((double)s2, (double)v[(long long)(off + i) * ldv + cc], val);
                     y[(long long)(off + i) * ldy + cc] = val;
                 }
             }
@@ -309,9 +329,15 @@ int mvm_rows_per_block(int dtype, int s) {
 }
 
 // Split the j range so the number of equal-cost blocks fills the chip's
-// resident slots with the least idle tail (blocks per CU assumed ~4).
-int mvm_pick_nsplit(int dtype, int nrb, int n_max) {
-    const int slots = 256 * 4;
+// resident slots (256 CUs x blocks resident per CU, set by the kernel's
+// register use) with the least idle tail.
+int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s) {
+    int per_cu = 4;
+    if (dtype != CIQ_F64) {
+        const int nsb = (s > 256 ? 256 : s + 15) / 16;
+        per_cu = nsb <= 2 ? 4 : nsb <= 8 ? 2 : 1;
+    }
+    const int slots = 256 * per_cu;
     const int max_split = (dtype == CIQ_F64) ? 16 : 8;
     int best = 1;
     double best_eff = 0.0;
@@ -341,7 +367,7 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
         MvmArgs g = a;
         g.s = (a.s - c0 < 256) ? a.s - c0 : 256;
         g.v = static_cast<const float*>(a.v) + c0;
-        g.y = static_cast<float*>(a.y) + c0;
+        g.y = static_cast<double*>(a.y) + c0;
         const int nsb = (g.s + 15) / 16;
         const hipError_t e = a.kernel == CIQ_KERNEL_RBF ? launch_f32_k<CIQ_KERNEL_RBF>(g, nsb, a.nrb, st)
                                                         : launch_f32_k<CIQ_KERNEL_MATERN52>(g, nsb, a.nrb, st);
@@ -380,26 +406,26 @@ template hipError_t launch_prep<double>(const double*, int, int, int, const doub
 // ----------------------------------------------------------------------------
 // Sum of split partials: out[i][c] = sum_k ypart[k][i][c].
 // ----------------------------------------------------------------------------
-template <typename T>
-__global__ void reduce_splits_kernel(const T* ypart, long long ysplit, int nsplit, int ldy, int n,
-                                     int s, T* out, int ldo) {
+template <typename TO>
+__global__ void reduce_splits_kernel(const double* ypart, long long ysplit, int nsplit, int ldy, int n,
+                                     int s, TO* out, int ldo) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)n * s) return;
     const int i = (int)(e / s), c = (int)(e - (long long)i * s);
-    T acc = ypart[(long long)i * ldy + c];
+    double acc = ypart[(long long)i * ldy + c];
     for (int k = 1; k < nsplit; ++k) acc += ypart[k * ysplit + (long long)i * ldy + c];
-    out[(long long)i * ldo + c] = acc;
+    out[(long long)i * ldo + c] = (TO)acc;
 }
 
-template <typename T>
-hipError_t launch_reduce_splits(const T* ypart, long long ysplit, int nsplit, int ldy, int n, int s,
-                                T* out, int ldo, hipStream_t st) {
+template <typename TO>
+hipError_t launch_reduce_splits(const double* ypart, long long ysplit, int nsplit, int ldy, int n, int s,
+                                TO* out, int ldo, hipStream_t st) {
     const long long total = (long long)n * s;
-    hipLaunchKernelGGL(reduce_splits_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(reduce_splits_kernel<TO>, dim3((int)((total + 255) / 256)), dim3(256), 0, st,
                        ypart, ysplit, nsplit, ldy, n, s, out, ldo);
     return hipGetLastError();
 }
-template hipError_t launch_reduce_splits<float>(const float*, long long, int, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_reduce_splits<float>(const double*, long long, int, int, int, int, float*, int, hipStream_t);
 template hipError_t launch_reduce_splits<double>(const double*, long long, int, int, int, int, double*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
@@ -486,7 +512,6 @@ hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, c
     hipLaunchKernelGGL(dots_kernel<T>, grid, dim3(256), 0, st, d, y, ysplit, nsplit, q, qp, phase);
     return hipGetLastError();
 }
-template hipError_t launch_dots<float>(const Dev&, const float*, long long, int, const float*, const float*, int, hipStream_t);
 template hipError_t launch_dots<double>(const Dev&, const double*, long long, int, const double*, const double*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
@@ -671,7 +696,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long long ysplit, int nsplit,
                                                      const T* qcur, T* qprev, const T* m_prev,
                                                      T* m_cur, T* acc, T* solves, long long mstride,
-                                                     int TS) {
+                                                     int TS, float* q32) {
     extern __shared__ char smem[];
     if (!d.st->live) return;
     const int RL = 256 / TS;
@@ -728,14 +753,16 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
             for (int k = 1; k < nsplit; ++k) ys += (double)y[k * ysplit + idx];
             const T vT = (T)ys - bj * qprev[idx];     // same arithmetic as the inner products
             const T v = vT - al * qj;
-            qprev[idx] = v * ib;
+            const T qn = v * ib;
+            qprev[idx] = qn;
+            if (q32) q32[idx] = (float)qn;      // operand copy for the FP32 kernel product
         }
     }
 }
 
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur, T* qprev,
-                         const T* m_prev, T* m_cur, T* acc, T* solves, int max_n, hipStream_t st) {
+                         const T* m_prev, T* m_cur, T* acc, T* solves, float* q32, int max_n, hipStream_t st) {
     const size_t per = 5 * sizeof(T) + sizeof(int);   // LDS bytes per (shift, column)
     int TS = col_tile(d.s);
     while (TS > 1 && (size_t)d.Q * TS * per > 49152) TS >>= 1;   // coefficient tile <= 48 KB LDS
@@ -747,20 +774,18 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
     const size_t shm = (size_t)d.Q * TS * per;
     const long long mstride = (long long)d.rows_total * d.s;
     hipLaunchKernelGGL(update_kernel<T>, grid, dim3(256), shm, st, d, y, ysplit, nsplit, qcur, qprev,
-                       m_prev, m_cur, acc, solves, mstride, TS);
+                       m_prev, m_cur, acc, solves, mstride, TS, q32);
     return hipGetLastError();
 }
-template hipError_t launch_update<float>(const Dev&, const float*, long long, int, const float*, float*,
-                                         const float*, float*, float*, float*, int, hipStream_t);
 template hipError_t launch_update<double>(const Dev&, const double*, long long, int, const double*, double*,
-                                          const double*, double*, double*, double*, int, hipStream_t);
+                                          const double*, double*, double*, double*, float*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Start of a run: q_1 = b / ||b|| (0 for a zero column), q_0 = 0, acc = 0.
 // The caller has copied B into q and zeroed the direction/solve buffers.
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc) {
+__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)d.rows_total * d.s;
     if (e >= total) return;
@@ -768,42 +793,45 @@ __global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc) {
     int p = 0;
     while (p + 1 < d.nprob && d.row_off[p + 1] <= row) ++p;
     const T inv = (T)d.inv_beta_next[p * d.s + c];
-    q[e] = q[e] * inv;
+    const T qv = q[e] * inv;
+    q[e] = qv;
+    if (q32) q32[e] = (float)qv;
     qprev[e] = (T)0;
     acc[e] = (T)0;
 }
 
 template <typename T>
-hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, int rows, hipStream_t st) {
+hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows, hipStream_t st) {
     const long long total = (long long)rows * d.s;
     hipLaunchKernelGGL(init_vectors_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, d, q,
-                       qprev, acc);
+                       qprev, acc, q32);
     return hipGetLastError();
 }
-template hipError_t launch_init_vectors<float>(const Dev&, float*, float*, float*, int, hipStream_t);
-template hipError_t launch_init_vectors<double>(const Dev&, double*, double*, double*, int, hipStream_t);
+template hipError_t launch_init_vectors<double>(const Dev&, double*, double*, double*, float*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Strided copy, fill, counter-based random start vector.
 // ----------------------------------------------------------------------------
-template <typename T>
-__global__ void copy2d_kernel(const T* src, int ld_src, int n, int s, T* dst, int ld_dst) {
+template <typename TI, typename TO>
+__global__ void copy2d_kernel(const TI* src, int ld_src, int n, int s, TO* dst, int ld_dst) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)n * s) return;
     const int i = (int)(e / s), c = (int)(e - (long long)i * s);
-    dst[(long long)i * ld_dst + c] = src[(long long)i * ld_src + c];
+    dst[(long long)i * ld_dst + c] = (TO)src[(long long)i * ld_src + c];
 }
 
-template <typename T>
-hipError_t launch_copy_in(const T* src, int ld_src, int n, int s, T* dst, int ld_dst, hipStream_t st) {
+template <typename TI, typename TO>
+hipError_t launch_copy(const TI* src, int ld_src, int n, int s, TO* dst, int ld_dst, hipStream_t st) {
     const long long total = (long long)n * s;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(copy2d_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, src, ld_src,
-                       n, s, dst, ld_dst);
+    hipLaunchKernelGGL((copy2d_kernel<TI, TO>), dim3((int)((total + 255) / 256)), dim3(256), 0, st, src,
+                       ld_src, n, s, dst, ld_dst);
     return hipGetLastError();
 }
-template hipError_t launch_copy_in<float>(const float*, int, int, int, float*, int, hipStream_t);
-template hipError_t launch_copy_in<double>(const double*, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_copy<float, float>(const float*, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_copy<double, double>(const double*, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_copy<float, double>(const float*, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_copy<double, float>(const double*, int, int, int, float*, int, hipStream_t);
 
 template <typename T>
 __global__ void fill_kernel(T* p, size_t count, T value) {
