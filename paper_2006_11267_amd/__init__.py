@@ -14,4 +14,6 @@ from .ops import (  # noqa: F401
     ciq_setup,
     ciq_sqrt_mvm,
     ciq_version,
+    ciq_backward,
 )
+from .autograd import CIQFunction, ciq_apply  # noqa: F401

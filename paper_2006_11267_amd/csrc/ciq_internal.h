@@ -82,6 +82,7 @@ struct MvmArgs {
     int kernel;
     int dp;
     int nsplit;
+    int rt;                  // FP32 product: row tiles of 16 per wave (1 or 2)
     // single problem (wl == nullptr)
     int n;
     double o2, s2;
@@ -97,7 +98,7 @@ struct MvmArgs {
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------
-int mvm_rows_per_block(int dtype, int s);
+int mvm_rows_per_block(int dtype, int s, int rt);
 int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s);
 hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st);
 
@@ -137,20 +138,16 @@ hipError_t launch_fill(T* p, size_t count, T value, hipStream_t st);
 template <typename T>
 hipError_t launch_splitmix(T* v, int n, uint64_t seed, int ld, hipStream_t st);
 
-// gradient tile pass: out[k] += sum_ij W_ij * dK_ij/dtheta_k, W = sum_q w_q G_q A_q^T
-struct GradArgs {
-    const float* xh;        // scaled points (kernel-specific scaling), n x dp
-    const float* xr;        // raw points scaled by 1/l (for (x_d - x'_d)^2 / l^2), n x dp
-    const float* gq;        // [n][Q][s] backward solves, pre-multiplied by w_q
-    const float* aq;        // [n][Q][s] forward solves
-    int n, dp, d, qs;       // qs = Q * s
-    int kernel;
-    double* partial;        // [gridDim.x * gridDim.y][d + 2]
-};
-hipError_t launch_grad_tiles(const GradArgs& a, int* nblocks_out, hipStream_t st);
-
+// ---- backward tile pass (grad.hip) ------------------------------------------
+int grad_rows_pad(int n);
+int grad_k_pad(int k);
+// U/V rows: [w_q g_q(i,:) | -G(i,:)] and [a_q(i,:) | A(i,:)], zero padded to
+// grad_rows_pad(n) x grad_k_pad((Q + sqrt_mode) * s)
 template <typename T>
-hipError_t launch_weighted_sum(const T* solves, int n, int Q, int s, const double* w_dev,
-                               T* out, int ldo, hipStream_t st);
+hipError_t launch_build_uv(const double* gq, const T* aq, const T* g, int ldg, const double* w_dev, int n,
+                           int Q, int s, int sqrt_mode, double* U, double* V, hipStream_t st);
+// partial[block][0..dp) = sum W_ij h (u_id - u_jd)^2, [dp] = sum W_ij k, [dp+1] = sum W_ii
+hipError_t launch_grad_pass(int kernel, const double* U, const double* V, int kpad, const double* pts,
+                            int n, int dp, double* partial, int* nblocks, hipStream_t st);
 
 }  // namespace ciq

@@ -7,6 +7,8 @@
 // host polls a device "done" flag every few iterations) -> combine.
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -107,7 +109,27 @@ struct Sizer {
     }
 };
 
-int pad_dims(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : 16; }
+// Point padding: the FP32 product is instantiated for 4/6/8/10/12/16 dims, the
+// FP64 product and the gradient pass for 4/8/12/16.
+int pad_dims(int d, int dtype) {
+    if (dtype != CIQ_F64 && dtype >= 0)
+        return d <= 4 ? 4 : d <= 6 ? 6 : d <= 8 ? 8 : d <= 10 ? 10 : d <= 12 ? 12 : 16;
+    return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : 16;
+}
+
+// ---- kernel-product autotuner ---------------------------------------------
+// Candidates: RT (16-row tiles per wave, 1 or 2; register use vs operand
+// reuse) with the split of the j range that fills the chip for that RT. Each
+// candidate's product is timed with HIP events on the problem itself the
+// first time a (dtype, kernel, dims, column blocks, log2 N) key is met; the
+// winner is cached for the process.
+struct TuneKey {
+    int dtype, kernel, dp, nsb, nlog;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dtype, kernel, dp, nsb, nlog) < std::tie(o.dtype, o.kernel, o.dp, o.nsb, o.nlog);
+    }
+};
+std::map<TuneKey, int> g_tuned_rt;   // guarded by the device scratch lock
 
 bool valid_problem(const ciq_problem* p) {
     if (!p || !p->x || !p->lengthscale) return false;
@@ -152,7 +174,7 @@ struct Run {
     int nprob = 1, s = 1, Q = 0, max_iter = 0, rows_total = 0, max_n = 0;
     double tol = 0.0;
     int bounds_mode = 0;
-    int nsplit = 1, nrb = 0;
+    int nsplit = 1, nrb = 0, rt = 2, nsplit_alloc = 1, nrb_alloc = 1;
     bool keep_solves = false;
     // device memory: points in the I/O type T, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
@@ -185,7 +207,7 @@ struct Run {
         if (with_xh) xh = a.template take<T>((size_t)rows_total * dp);
         qbuf[0] = a.template take<double>(vec);
         qbuf[1] = a.template take<double>(vec);
-        ypart = a.template take<double>(vec * nsplit);
+        ypart = a.template take<double>(vec * nsplit_alloc);
         if (Q > 0) {
             mbuf[0] = a.template take<double>(vec * Q);
             mbuf[1] = a.template take<double>(vec * Q);
@@ -193,7 +215,7 @@ struct Run {
         acc = a.template take<double>(vec);
         if (keep_solves) solves = a.template take<double>(vec * Q);
         if (sizeof(T) == 4) q32 = a.template take<float>(vec);
-        wl = a.template take<WorkItem>(std::max(nrb, 1));
+        wl = a.template take<WorkItem>(std::max(nrb_alloc, 1));
         pn = a.template take<int>(nprob);
         poff = a.template take<int>(nprob);
         po2 = a.template take<float>(nprob);
@@ -224,14 +246,28 @@ struct Run {
         d.st = a.template take<IterState>(1);
     }
 
-    void configure(int rows_per_block) {
-        int rows_per_blk_dots = 256 / std::max(1, std::min(64, s));
-        (void)rows_per_blk_dots;
+    int rows_per_block() const { return mvm_rows_per_block(dtype, s, rt); }
+
+    void configure(int rt_) {
+        rt = rt_;
         d.dots_blocks = std::min(64, std::max(1, (max_n + 255) / 256));
+        const int rpb = rows_per_block();
         nrb = 0;
-        for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rows_per_block - 1) / rows_per_block;
+        for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rpb - 1) / rpb;
         nsplit = mvm_pick_nsplit(dtype, nrb, max_n, s);
         ysplit = (long long)rows_total * s;
+    }
+
+    // size the partial-product buffer and the work list for every RT candidate
+    void plan(int rt_) {
+        nsplit_alloc = 1;
+        nrb_alloc = 1;
+        for (int r = 1; r <= 2; ++r) {
+            configure(r);
+            nsplit_alloc = std::max(nsplit_alloc, nsplit);
+            nrb_alloc = std::max(nrb_alloc, nrb);
+        }
+        configure(rt_);
     }
 
     void fill_dev() {
@@ -250,10 +286,11 @@ struct Run {
         d.bounds_mode = bounds_mode;
     }
 
-    int upload_tables(hipStream_t st, int rows_per_block) {
+    int upload_tables(hipStream_t st) {
+        const int rpb = rows_per_block();
         std::vector<WorkItem> h_wl;
         for (int p = 0; p < nprob; ++p) {
-            const int nb = (h_n[p] + rows_per_block - 1) / rows_per_block;
+            const int nb = (h_n[p] + rpb - 1) / rpb;
             for (int r = 0; r < nb; ++r) h_wl.push_back(WorkItem{p, r});
         }
         HIPCHK(hipMemcpyAsync(wl, h_wl.data(), h_wl.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
@@ -277,6 +314,7 @@ struct Run {
         a.kernel = kernel;
         a.dp = dp;
         a.nsplit = nsplit;
+        a.rt = rt;
         a.n = h_n[0];
         a.o2 = h_o2d[0];
         a.s2 = h_s2d[0];
@@ -354,6 +392,51 @@ struct Run {
     // the combined solution lives in acc, the per-shift solves in `solves`.
 };
 
+// Pick RT for this run (see TuneKey). `operand` holds any n x s data in the
+// product's input type; the timed launches write only the partial buffer.
+template <typename T>
+int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
+    const int nsb = (std::min(r.s, 256) + 15) / 16;
+    if (r.dtype == CIQ_F64 || nsb >= 8) {
+        r.configure(r.dtype == CIQ_F64 ? 2 : 1);
+        return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
+    }
+    int nlog = 0;
+    while ((1 << (nlog + 1)) <= r.rows_total) ++nlog;
+    const TuneKey key{r.dtype, r.kernel, r.dp, nsb, nlog};
+    auto it = g_tuned_rt.find(key);
+    if (it == g_tuned_rt.end()) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        int best = 2;
+        for (int cand = 1; cand <= 2; ++cand) {
+            r.configure(cand);
+            if (r.nprob > 1) STCHK(r.upload_tables(st));
+            MvmArgs a = r.mvm_args(operand, r.ypart);
+            a.done = nullptr;
+            a.prob_done = nullptr;
+            HIPCHK(launch_mvm(r.dtype, a, st));   // warm-up
+            HIPCHK(hipEventRecord(e0, st));
+            for (int k = 0; k < 2; ++k) HIPCHK(launch_mvm(r.dtype, a, st));
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        it = g_tuned_rt.emplace(key, best).first;
+    }
+    r.configure(it->second);
+    return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
+}
+
 template <typename T>
 int setup_points(Run<T>& r, const ciq_problem* probs, int dtype, hipStream_t st) {
     for (int p = 0; p < r.nprob; ++p) {
@@ -366,7 +449,8 @@ int setup_points(Run<T>& r, const ciq_problem* probs, int dtype, hipStream_t st)
 }
 
 template <typename T>
-void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob) {
+void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob, int dtype) {
+    r.dtype = dtype;
     r.nprob = nprob;
     r.h_n.resize(nprob);
     r.h_off.resize(nprob);
@@ -388,7 +472,7 @@ void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob) {
     }
     r.rows_total = off;
     r.max_n = maxn;
-    r.dp = pad_dims(maxd);
+    r.dp = pad_dims(maxd, r.dtype);
     r.kernel = probs[0].kernel;
 }
 
@@ -414,26 +498,24 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
 
     // ---- sizing: bounds run (s = 1, Q = 0) and main run share the points ----
     Run<T> main;
-    fill_problem_tables(main, probs, nprob);
+    fill_problem_tables(main, probs, nprob, dtype);
     main.dtype = dtype;
     main.s = s;
     main.Q = o->q;
     main.max_iter = o->max_iter;
     main.tol = o->tol;
     main.keep_solves = (solves_out != nullptr);
-    const int rpb_main = mvm_rows_per_block(dtype, s);
-    main.configure(rpb_main);
+    main.plan(2);
 
     Run<T> bnd;
-    fill_problem_tables(bnd, probs, nprob);
+    fill_problem_tables(bnd, probs, nprob, dtype);
     bnd.dtype = dtype;
     bnd.s = 1;
     bnd.Q = 0;
     bnd.max_iter = steps;
     bnd.tol = 0.0;
     bnd.bounds_mode = 1;
-    const int rpb_b = mvm_rows_per_block(dtype, 1);
-    bnd.configure(rpb_b);
+    bnd.plan(2);
 
     Sizer sz;
     main.layout(sz, true);
@@ -455,7 +537,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     main.fill_dev();
     bnd.fill_dev();
 
-    STCHK(main.upload_tables(st, rpb_main));
+    STCHK(main.upload_tables(st));
     STCHK(setup_points(main, probs, dtype, st));
 
     std::vector<double> lmin(nprob), lmax(nprob);
@@ -480,7 +562,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
             lmax[p] = o->lambda_max;
         }
     } else {
-        STCHK(bnd.upload_tables(st, rpb_b));
+        STCHK(bnd.upload_tables(st));
         for (int p = 0; p < nprob; ++p)
             HIPCHK(launch_splitmix<double>(bnd.qbuf[0] + bnd.h_off[p], bnd.h_n[p], o->seed + 7919ull * p, 1, st));
         int cnt = 0, dummy_n = 0;
@@ -505,7 +587,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
             if (!(lmin[p] > 0.0) || !(lmax[p] >= lmin[p]) || !std::isfinite(lmax[p])) return CIQ_ENUMERIC;
         }
         // the bounds run reused the scratch after the points; restore the main tables
-        STCHK(main.upload_tables(st, rpb_main));
+        STCHK(main.upload_tables(st));
     }
 
     // ---- shifts / weights --------------------------------------------------
@@ -522,6 +604,12 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         HIPCHK((launch_copy<T, double>(static_cast<const T*>(b_ptrs[p]), ldb, main.h_n[p], s,
                                        main.qbuf[0] + (size_t)main.h_off[p] * s, s, st)));
     HIPCHK(hipStreamSynchronize(st));  // th/wh are pageable host vectors
+    if (main.q32) {
+        HIPCHK((launch_copy<double, float>(main.qbuf[0], s, main.rows_total, s, main.q32, s, st)));
+        STCHK(tune_rt(main, main.q32, st));
+    } else {
+        STCHK(tune_rt(main, main.qbuf[0], st));
+    }
 
     STCHK(main.iterate(st, check_every, pinned, &mvm_count, profile ? evs.data() : nullptr,
                        profile ? check_every : 0, &mvm_ms, &mvm_timed));
@@ -605,6 +693,133 @@ int check_solve_args(const ciq_problem* p, const ciq_opts* o, const void* b, int
     return CIQ_OK;
 }
 
+// Backward of a forward call (Sec. 3.3): one msMINRES run on G' = G (inverse
+// root) or K G (root) with the forward's shifts, dB = sum_q w_q g_q, then the
+// tile pass contracting W = sum_q w_q g_q a_q^T (+ the root's direct term)
+// with dK/dtheta.
+template <typename T>
+int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const double* t, const double* w,
+                  const void* solves, const void* g, int s, int ldg, void* db, int lddb, double* dls,
+                  double* do2, double* dnoise, ciq_info* info, hipStream_t st) {
+    int dev;
+    STCHK(get_device(&dev));
+    ScratchLock lock(dev);
+    const int dtype = o->dtype;
+    const int Q = o->q;
+    const int n = p->n;
+    const bool sqrt_mode = (mode == CIQ_SQRT);
+    const bool want_hyper = dls || do2 || dnoise;
+
+    Run<T> r;
+    fill_problem_tables(r, p, 1, dtype);
+    r.dtype = dtype;
+    r.s = s;
+    r.Q = Q;
+    r.max_iter = o->max_iter;
+    r.tol = o->tol;
+    r.keep_solves = true;
+    r.plan(2);
+
+    const int kpad = grad_k_pad((Q + (sqrt_mode ? 1 : 0)) * s);
+    const int rows_pad = grad_rows_pad(n);
+    const int dpg = pad_dims(p->d, -1);   // gradient pass instantiations
+    const int nb = rows_pad / 64;
+    auto extra = [&](auto& a, double** U, double** V, double** pts, double** xd, double** part) {
+        *U = a.template take<double>(want_hyper ? (size_t)rows_pad * kpad : 1);
+        *V = a.template take<double>(want_hyper ? (size_t)rows_pad * kpad : 1);
+        *pts = a.template take<double>((size_t)n * dpg);
+        *xd = a.template take<double>((size_t)n * p->d);
+        *part = a.template take<double>((size_t)nb * nb * (dpg + 2));
+    };
+    double *U, *V, *pts, *xd, *part;
+    Sizer sz;
+    r.layout(sz, true);
+    extra(sz, &U, &V, &pts, &xd, &part);
+    void* base = nullptr;
+    STCHK(scratch_reserve(dev, sz.off + 4096, &base));
+    IterState* pinned = g_scratch[dev].pinned;
+    Carver c(base);
+    r.layout(c, true);
+    extra(c, &U, &V, &pts, &xd, &part);
+    r.fill_dev();
+    STCHK(r.upload_tables(st));
+    STCHK(setup_points(r, p, dtype, st));
+    HIPCHK(hipMemcpyAsync(r.t, t, Q * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(r.w, w, Q * sizeof(double), hipMemcpyHostToDevice, st));
+
+    // G' into the first Lanczos buffer (FP64)
+    if (sqrt_mode) {
+        MvmArgs a = r.mvm_args(g, r.ypart);
+        a.ldv = ldg;
+        a.done = nullptr;
+        HIPCHK(launch_mvm(dtype, a, st));
+        HIPCHK(launch_reduce_splits<double>(r.ypart, r.ysplit, r.nsplit, s, n, s, r.qbuf[0], s, st));
+    } else {
+        HIPCHK((launch_copy<T, double>(static_cast<const T*>(g), ldg, n, s, r.qbuf[0], s, st)));
+    }
+    HIPCHK(hipStreamSynchronize(st));   // t/w came from caller-owned host memory
+    int mvm_count = sqrt_mode ? 1 : 0, dummy_n = 0;
+    double dummy = 0.0;
+    STCHK(r.iterate(st, o->check_every > 0 ? o->check_every : 16, pinned, &mvm_count, nullptr, 0, &dummy,
+                    &dummy_n));
+    const int iters = pinned->iter;
+    if (db) HIPCHK((launch_copy<double, T>(r.acc, s, n, s, static_cast<T*>(db), lddb, st)));
+
+    double acc_h[CIQ_MAX_D + 2] = {0};
+    if (want_hyper) {
+        // points scaled by 1/l per dimension, in FP64
+        HIPCHK((launch_copy<T, double>(static_cast<const T*>(p->x), p->d, n, p->d, xd, p->d, st)));
+        double scale[CIQ_MAX_D];
+        for (int k = 0; k < p->d; ++k) scale[k] = 1.0 / p->lengthscale[p->n_lengthscale == 1 ? 0 : k];
+        HIPCHK(launch_prep<double>(xd, n, p->d, dpg, scale, pts, st));
+        HIPCHK(launch_build_uv<T>(r.solves, static_cast<const T*>(solves), static_cast<const T*>(g), ldg, r.w, n,
+                                  Q, s, sqrt_mode ? 1 : 0, U, V, st));
+        int nblocks = 0;
+        HIPCHK(launch_grad_pass(p->kernel, U, V, kpad, pts, n, dpg, part, &nblocks, st));
+        std::vector<double> hp((size_t)nblocks * (dpg + 2));
+        HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int b = 0; b < nblocks; ++b)
+            for (int k = 0; k < dpg + 2; ++k) acc_h[k] += hp[(size_t)b * (dpg + 2) + k];
+    }
+    // report of the backward msMINRES run
+    const size_t qn = (size_t)Q * s;
+    std::vector<double> relres(qn);
+    HIPCHK(hipMemcpyAsync(relres.data(), r.d.relres, qn * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memset(info, 0, sizeof(*info));
+    double mr = 0.0;
+    int conv = 1;
+    for (double v : relres) {
+        mr = std::max(mr, v);
+        if (!(v <= o->tol)) conv = 0;
+    }
+    info->iters = iters;
+    info->converged = conv;
+    info->q = Q;
+    info->mvm_count = mvm_count;
+    info->max_rel_residual = mr;
+    for (int q = 0; q < Q; ++q) {
+        info->t[q] = t[q];
+        info->w[q] = w[q];
+    }
+    if (want_hyper) {
+        const double o2 = p->outputscale;
+        if (dls) {
+            if (p->n_lengthscale == 1) {
+                double sum = 0.0;
+                for (int k = 0; k < p->d; ++k) sum += acc_h[k];
+                dls[0] = -o2 * sum / p->lengthscale[0];
+            } else {
+                for (int k = 0; k < p->d; ++k) dls[k] = -o2 * acc_h[k] / p->lengthscale[k];
+            }
+        }
+        if (do2) *do2 = -acc_h[dpg];
+        if (dnoise) *dnoise = -acc_h[dpg + 1];
+    }
+    return CIQ_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -636,9 +851,9 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
                    hipStream_t stream) {
     if (!valid_problem(p) || !valid_dtype(dtype) || !v || !y || s < 1 || ldv < s || ldy < s) return CIQ_EINVAL;
     if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) return CIQ_ENOTSUP;
-    const int dp = pad_dims(p->d);
+    const int dp = pad_dims(p->d, dtype);
     const size_t esz = (dtype == CIQ_F64) ? 8 : 4;
-    const int rpb = mvm_rows_per_block(dtype, s);
+    const int rpb = mvm_rows_per_block(dtype, s, 2);
     const int nrb = (p->n + rpb - 1) / rpb;
     const int nsplit = mvm_pick_nsplit(dtype, nrb, p->n, s);
     // stream-ordered scratch: scaled points + FP64 split partials (the FP32
@@ -672,6 +887,7 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     a.kernel = p->kernel;
     a.dp = dp;
     a.nsplit = nsplit;
+    a.rt = 2;
     a.n = p->n;
     a.o2 = p->outputscale;
     a.s2 = p->noise;
@@ -701,14 +917,13 @@ int ciq_eig_bounds(const ciq_problem* p, int dtype, int steps, const void* v0, u
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         Run<T> r;
-        fill_problem_tables(r, p, 1);
+        fill_problem_tables(r, p, 1, dtype);
         r.dtype = dtype;
         r.s = 1;
         r.Q = 0;
         r.max_iter = J;
         r.bounds_mode = 1;
-        const int rpb = mvm_rows_per_block(dtype, 1);
-        r.configure(rpb);
+        r.plan(2);
         Sizer sz;
         r.layout(sz, true);
         void* base = nullptr;
@@ -716,7 +931,7 @@ int ciq_eig_bounds(const ciq_problem* p, int dtype, int steps, const void* v0, u
         Carver c(base);
         r.layout(c, true);
         r.fill_dev();
-        STCHK(r.upload_tables(stream, rpb));
+        STCHK(r.upload_tables(stream));
         STCHK(setup_points(r, p, dtype, stream));
         if (v0)
             HIPCHK((launch_copy<T, double>(static_cast<const T*>(v0), 1, p->n, 1, r.qbuf[0], 1, stream)));
@@ -779,8 +994,19 @@ int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts*
 int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double* t, const double* w,
                  const void* solves, const void* g, int s, int ldg, void* db, int lddb, double* dlengthscale,
                  double* doutputscale, double* dnoise, ciq_info* info, hipStream_t stream) {
-    (void)p; (void)o; (void)mode; (void)t; (void)w; (void)solves; (void)g; (void)s; (void)ldg; (void)db;
-    (void)lddb; (void)dlengthscale; (void)doutputscale; (void)dnoise; (void)info; (void)stream;
+    if (!valid_problem(p) || !o || !t || !w || !solves || !g || !info) return CIQ_EINVAL;
+    if (!valid_dtype(o->dtype) || (mode != CIQ_INVSQRT && mode != CIQ_SQRT)) return CIQ_EINVAL;
+    if (s < 1 || ldg < s || (db && lddb < s)) return CIQ_EINVAL;
+    if (o->q < 1 || o->q > CIQ_MAX_Q || o->max_iter < 1 || !(o->tol >= 0.0) || !std::isfinite(o->tol))
+        return CIQ_EINVAL;
+    for (int q = 0; q < o->q; ++q)
+        if (!(t[q] > 0.0) || !(w[q] > 0.0) || !std::isfinite(t[q]) || !std::isfinite(w[q])) return CIQ_EINVAL;
+    if (o->dtype == CIQ_F64)
+        return backward_impl<double>(p, o, mode, t, w, solves, g, s, ldg, db, lddb, dlengthscale, doutputscale,
+                                     dnoise, info, stream);
+    if (o->dtype == CIQ_F32)
+        return backward_impl<float>(p, o, mode, t, w, solves, g, s, ldg, db, lddb, dlengthscale, doutputscale,
+                                    dnoise, info, stream);
     return CIQ_ENOTSUP;
 }
 

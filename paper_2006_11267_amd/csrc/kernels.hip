@@ -76,7 +76,11 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     constexpr int BN = 64;
     constexpr int S16 = NSB * 16;
     constexpr int VST = (NSB & 1) ? S16 : S16 + 16;  // LDS row stride: rows j, j+1 hit disjoint banks
-    __shared__ float xs[BN * DP];
+    constexpr int XE = BN * DP;                       // staged point floats per chunk
+    constexpr int XPT = (XE + 255) / 256;             // per thread
+    constexpr int VPT = BN * S16 / 256;               // staged V floats per thread
+    constexpr int VROWS = 256 / S16;                  // V rows covered by one pass of the block
+    __shared__ float xs[XE];
     __shared__ float vs[BN * VST];
 
     if (done_now(a.done)) return;
@@ -98,13 +102,14 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
         s2 = a.s2;
     }
     const int split = blockIdx.y;
-    const float* __restrict__ xh = static_cast<const float*>(a.xh);
-    const float* __restrict__ v = static_cast<const float*>(a.v);
-    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    const float* __restrict__ xh = static_cast<const float*>(a.xh) + (long long)off * DP;
+    const float* __restrict__ v = static_cast<const float*>(a.v) + (long long)off * a.ldv;
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit + (long long)off * a.ldy;
     const int s = a.s, ldv = a.ldv, ldy = a.ldy;
 
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int row0 = rb * BM + wave * 16 * RT;
 
     float xi[RT][DP];
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     for (int rt = 0; rt < RT; ++rt) {
         const int i = row0 + rt * 16 + (lane & 15);
 #pragma unroll
-        for (int k = 0; k < DP; ++k) xi[rt][k] = (i < n) ? xh[(long long)(off + i) * DP + k] : 0.0f;
+        for (int k = 0; k < DP; ++k) xi[rt][k] = (i < n) ? xh[(long long)i * DP + k] : 0.0f;
     }
 
     floatx4 acc[RT][NSB];
@@ -130,20 +135,39 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     const int c0 = (int)(((long long)split * nchunk) / a.nsplit);
     const int c1 = (int)(((long long)(split + 1) * nchunk) / a.nsplit);
 
-    for (int c = c0; c < c1; ++c) {
+    // register staging of the next chunk (loads in flight while the current
+    // chunk is computed); each thread owns fixed (row, column) slots
+    const int vr = tid / S16, vc = tid - (tid / S16) * S16;
+    const bool vcol_ok = vc < s;
+    float xreg[XPT], vreg[VPT];
+    auto fetch = [&](int c) {
         const int j0 = c * BN;
-        __syncthreads();
-        for (int e = threadIdx.x; e < BN * DP; e += 256) {
-            const int jj = e / DP;
-            const int j = j0 + jj;
-            xs[e] = (j < n) ? xh[(long long)(off + j0) * DP + e] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < XPT; ++k) {
+            const int e = tid + 256 * k;
+            const int j = j0 + e / DP;
+            xreg[k] = (e < XE && j < n) ? xh[(long long)j0 * DP + e] : 0.0f;
         }
-        for (int e = threadIdx.x; e < BN * S16; e += 256) {
-            const int jj = e / S16, cc = e - jj * S16;
-            const int j = j0 + jj;
-            vs[jj * VST + cc] = (j < n && cc < s) ? v[(long long)(off + j) * ldv + cc] : 0.0f;
+        const float* vp = v + (long long)(j0 + vr) * ldv + vc;
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int j = j0 + vr + k * VROWS;
+            vreg[k] = (vcol_ok && j < n) ? vp[(long long)k * VROWS * ldv] : 0.0f;
         }
+    };
+    if (c0 < c1) fetch(c0);
+
+    for (int c = c0; c < c1; ++c) {
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < XPT; ++k) {
+            const int e = tid + 256 * k;
+            if (e < XE) xs[e] = xreg[k];
+        }
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
+        __syncthreads();
+        if (c + 1 < c1) fetch(c + 1);
 #pragma unroll
         for (int jb = 0; jb < BN / 16; ++jb) {
 #pragma unroll
@@ -191,9 +215,9 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
             for (int r = 0; r < 4; ++r) {
                 const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;
                 if (i < n && cc < s) {
-                    double val = (double)o2 * accd[rt][sb][r];
-                    if (split == 0) val = fma((double)s2, (double)v[(long long)(off + i) * ldv + cc], val);
-                    y[(long long)(off + i) * ldy + cc] = val;
+                    double val = o2 * accd[rt][sb][r];
+                    if (split == 0) val = fma(s2, (double)v[(long long)i * ldv + cc], val);
+                    y[(long long)i * ldy + cc] = val;
                 }
             }
         }
@@ -273,9 +297,11 @@ __global__ __launch_bounds__(256) void mvm_f64_kernel(MvmArgs a) {
 
 template <int KERNEL, int DP, int NSB>
 hipError_t launch_f32_nsb(const MvmArgs& a, int grid_x, hipStream_t st) {
-    constexpr int RT = (NSB <= 4) ? 2 : 1;
     dim3 grid(grid_x, a.nsplit);
-    hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, RT>), grid, dim3(256), 0, st, a);
+    if (a.rt == 1 || NSB >= 8)
+        hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 1>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 2>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -296,7 +322,9 @@ template <int KERNEL>
 hipError_t launch_f32_k(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
     switch (a.dp) {
         case 4: return launch_f32_dp<KERNEL, 4>(a, nsb, grid_x, st);
+        case 6: return launch_f32_dp<KERNEL, 6>(a, nsb, grid_x, st);
         case 8: return launch_f32_dp<KERNEL, 8>(a, nsb, grid_x, st);
+        case 10: return launch_f32_dp<KERNEL, 10>(a, nsb, grid_x, st);
         case 12: return launch_f32_dp<KERNEL, 12>(a, nsb, grid_x, st);
         default: return launch_f32_dp<KERNEL, 16>(a, nsb, grid_x, st);
     }
@@ -314,7 +342,9 @@ template <int KERNEL>
 hipError_t launch_f64_k(const MvmArgs& a, hipStream_t st) {
     switch (a.dp) {
         case 4: return launch_f64_dp<KERNEL, 4>(a, st);
+        case 6:
         case 8: return launch_f64_dp<KERNEL, 8>(a, st);
+        case 10:
         case 12: return launch_f64_dp<KERNEL, 12>(a, st);
         default: return launch_f64_dp<KERNEL, 16>(a, st);
     }
@@ -322,10 +352,10 @@ hipError_t launch_f64_k(const MvmArgs& a, hipStream_t st) {
 
 }  // namespace
 
-int mvm_rows_per_block(int dtype, int s) {
+int mvm_rows_per_block(int dtype, int s, int rt) {
     if (dtype == CIQ_F64) return 64;
-    const int nsb = (s + 15) / 16;
-    return (nsb <= 4) ? 128 : 64;
+    const int nsb = (s > 256 ? 256 : s + 15) / 16;
+    return (nsb <= 4 && rt == 2) ? 128 : 64;
 }
 
 // Split the j range so the number of equal-cost blocks fills the chip's

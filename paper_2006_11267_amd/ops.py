@@ -169,3 +169,41 @@ def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tens
             "ciq_invsqrt_mvm_batched")
     del keeps
     return outs, [i.as_dict() for i in infos]
+
+
+def ciq_backward(problem: Problem, g: torch.Tensor, t, w, solves: torch.Tensor, mode: str = "invsqrt",
+                 max_iter: int = 200, tol: float = 1e-4, precision: Optional[str] = None, want_b: bool = True,
+                 want_hyper: bool = True, check_every: int = 0):
+    """VJP of a forward call: returns (dB or None, dlengthscale, doutputscale, dnoise, info)."""
+    lib = L.load()
+    code = _dtype_code(problem.x, precision)
+    g2 = g if g.dim() == 2 else g.reshape(-1, 1)
+    if g2.stride(1) != 1:
+        g2 = g2.contiguous()
+    n, s = g2.shape
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    q = t.size
+    tc = (ctypes.c_double * q)(*t.tolist())
+    wc = (ctypes.c_double * q)(*w.tolist())
+    db = torch.empty((n, s), dtype=_elem_dtype(code), device=g.device) if want_b else None
+    nls = np.asarray(problem.lengthscale).size
+    dls = (ctypes.c_double * nls)()
+    do2 = ctypes.c_double()
+    dn = ctypes.c_double()
+    p, keep = problem.c_struct()
+    o = _opts(code, q, max_iter, tol, check_every=check_every)
+    info = L.ciq_info()
+    mode_code = L.CIQ_SQRT if mode == "sqrt" else L.CIQ_INVSQRT
+    sol = solves.contiguous()
+    L.check(lib.ciq_backward(ctypes.byref(p), ctypes.byref(o), mode_code, tc, wc, ctypes.c_void_p(sol.data_ptr()),
+                             ctypes.c_void_p(g2.data_ptr()), s, g2.stride(0),
+                             ctypes.c_void_p(db.data_ptr()) if db is not None else None, s,
+                             dls if want_hyper else None, ctypes.byref(do2) if want_hyper else None,
+                             ctypes.byref(dn) if want_hyper else None, ctypes.byref(info), _stream()),
+            "ciq_backward")
+    del keep
+    dB = db.reshape(g.shape) if db is not None else None
+    if not want_hyper:
+        return dB, None, None, None, info.as_dict()
+    return dB, np.array(dls[:]), do2.value, dn.value, info.as_dict()
