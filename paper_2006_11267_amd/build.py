@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libciq.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "grad.hip", "elliptic.cpp", "host.cpp"]
+SOURCES = ["mvm_f32_rbf_iso.hip", "mvm_f32_rbf_ard.hip", "mvm_f32_m52_iso.hip", "mvm_f32_m52_ard.hip",
+           "kernels.hip", "grad.hip", "elliptic.cpp", "host.cpp"]
 
 # Packed FP32 (v_pk_*_f32) is disabled for every device pass.
 HIPFLAGS = [
@@ -50,7 +51,7 @@ def build_library(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]

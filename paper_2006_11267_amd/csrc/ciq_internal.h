@@ -46,6 +46,7 @@ struct Dev {
     // dots
     int dots_blocks;        // partial blocks per problem
     double* dots;           // [nprob][dots_blocks][s][2] (alpha, beta^2 partials)
+    double* colsum;         // [2][ncol]: block-summed alpha, beta^2
     // column state
     double* beta1;          // ||b_g||
     double* beta_cur;       // beta_j  (couples q_{j-1}, q_j)
@@ -73,7 +74,8 @@ struct WorkItem {
 
 // Arguments of one kernel-product launch Y = K V (split over the j range).
 struct MvmArgs {
-    const void* xh;          // scaled, zero-padded points: rows x dp
+    const void* xh;          // zero-padded FP64 points: rows x dp (FP64 path: pre-scaled;
+                             // FP32 path: raw coordinates, scaled after subtraction)
     const void* v;           // rows x s (ld = ldv); float (FP32 path) or double
     void* y;                 // double partial outputs: nsplit x rows x s (ld = ldy)
     long long ysplit;        // elements between split partials
@@ -83,6 +85,9 @@ struct MvmArgs {
     int dp;
     int nsplit;
     int rt;                  // FP32 product: row tiles of 16 per wave (1 or 2)
+    int ard;                 // FP32 product: per-dimension scales differ
+    double scale[CIQ_MAX_D]; // FP32 product: per-dimension scale of coordinate differences
+    const double* pscale;    // batched: [nprob][CIQ_MAX_D] scales
     // single problem (wl == nullptr)
     int n;
     double o2, s2;
@@ -97,13 +102,17 @@ struct MvmArgs {
     const int* done;         // global done flag or nullptr
 };
 
-// ---- launchers (kernels.hip) ------------------------------------------------
+// ---- launchers (kernels.hip, mvm_f32_*.hip) ---------------------------------
+hipError_t launch_mvm_f32_rbf_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
+hipError_t launch_mvm_f32_rbf_ard(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
+hipError_t launch_mvm_f32_m52_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
+hipError_t launch_mvm_f32_m52_ard(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
 int mvm_rows_per_block(int dtype, int s, int rt);
 int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s);
 hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st);
 
-template <typename T>
-hipError_t launch_prep(const T* x, int n, int d, int dp, const double* scale, T* xh,
+template <typename TI>
+hipError_t launch_prep(const TI* x, int n, int d, int dp, const double* scale, double* xh,
                        hipStream_t st);
 
 // ypart: double partials of the kernel product (both paths accumulate in FP64)
@@ -115,6 +124,7 @@ template <typename T>
 hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q,
                        const T* qp, int phase, hipStream_t st);
 
+hipError_t launch_colsum(const Dev& d, int k, hipStream_t st);
 hipError_t launch_scalar_init(const Dev& d, hipStream_t st);
 hipError_t launch_scalar(const Dev& d, hipStream_t st);
 

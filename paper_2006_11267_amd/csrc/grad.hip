@@ -104,7 +104,9 @@ __global__ __launch_bounds__(256) void grad_tiles_kernel(const double* U, const 
         }
     }
 
-    // epilogue: this lane holds W[i][j] for i = wi + 16a + 4(l/16) + r, j = wj + 16b + l%16
+    // epilogue: the FP64 16x16x4 MFMA leaves W[i][j] in lane l, register r for
+    // i = wi + 16a + l/16 + 4r, j = wj + 16b + l%16 (checked on gfx950 with an
+    // in-bounds layout probe; the FP32 16x16x4 layout differs: i = 4(l/16) + r)
     double g[DP + 2];
 #pragma unroll
     for (int k = 0; k < DP + 2; ++k) g[k] = 0.0;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(256) void grad_tiles_kernel(const double* U, const 
         for (int a = 0; a < 2; ++a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int il = wi + 16 * a + 4 * (lane >> 4) + r;
+                const int il = wi + 16 * a + (lane >> 4) + 4 * r;
                 const int i = i0 + il, j = j0 + jl;
                 if (i >= n || j >= n) continue;
                 const double wij = acc[a][b][r];

@@ -29,7 +29,6 @@ namespace {
 
 constexpr int kMaxDevices = 64;
 constexpr double kSqrt5 = 2.23606797749978969640917366873;
-constexpr double kLog2e = 1.44269504088896340735992468100;
 
 #define HIPCHK(expr)                        \
     do {                                    \
@@ -148,11 +147,9 @@ bool valid_dtype(int dt) { return dt == CIQ_F64 || dt == CIQ_F32 || dt == CIQ_BF
 // Per-dimension multipliers applied to X so the device kernels evaluate k from
 // a plain squared distance (see kfun32 / kfun64 in kernels.hip).
 void point_scale(const ciq_problem* p, int dtype, double* scale) {
-    double c;
-    if (p->kernel == CIQ_KERNEL_RBF)
-        c = (dtype == CIQ_F64) ? 1.0 : std::sqrt(0.5 * kLog2e);
-    else
-        c = kSqrt5;
+    (void)dtype;
+    // RBF: k = exp(-r2/2) with r2 of (x/l); Matern-5/2: rho = sqrt(r2) with r2 of (sqrt5 x/l)
+    const double c = (p->kernel == CIQ_KERNEL_RBF) ? 1.0 : kSqrt5;
     for (int k = 0; k < p->d; ++k) {
         const double l = p->lengthscale[p->n_lengthscale == 1 ? 0 : k];
         scale[k] = c / l;
@@ -176,10 +173,10 @@ struct Run {
     int bounds_mode = 0;
     int nsplit = 1, nrb = 0, rt = 2, nsplit_alloc = 1, nrb_alloc = 1;
     bool keep_solves = false;
-    // device memory: points in the I/O type T, every msMINRES vector in FP64
+    // device memory: points in FP64, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
     // consumes an FP32 copy q32 of the current Lanczos vector)
-    T* xh = nullptr;
+    double* xh = nullptr;
     double* qbuf[2] = {nullptr, nullptr};
     double* ypart = nullptr;
     double* mbuf[2] = {nullptr, nullptr};
@@ -191,6 +188,7 @@ struct Run {
     int* poff = nullptr;
     float* po2 = nullptr;
     float* ps2 = nullptr;
+    double* pscale = nullptr;  // [nprob][CIQ_MAX_D] FP32-product difference scales
     double* t = nullptr;
     double* w = nullptr;
     Dev d{};
@@ -198,13 +196,15 @@ struct Run {
     // host mirrors
     std::vector<int> h_n, h_off;
     std::vector<float> h_o2, h_s2;
+    std::vector<double> h_scale;
     std::vector<double> h_o2d, h_s2d;
+    int ard = 0;
 
     template <typename A>
     void layout(A& a, bool with_xh) {
         const int ncol = nprob * s;
         const size_t vec = (size_t)rows_total * s;
-        if (with_xh) xh = a.template take<T>((size_t)rows_total * dp);
+        if (with_xh) xh = a.template take<double>((size_t)rows_total * dp);
         qbuf[0] = a.template take<double>(vec);
         qbuf[1] = a.template take<double>(vec);
         ypart = a.template take<double>(vec * nsplit_alloc);
@@ -220,9 +220,11 @@ struct Run {
         poff = a.template take<int>(nprob);
         po2 = a.template take<float>(nprob);
         ps2 = a.template take<float>(nprob);
+        pscale = a.template take<double>((size_t)nprob * CIQ_MAX_D);
         t = a.template take<double>(std::max(nprob * Q, 1));
         w = a.template take<double>(std::max(nprob * Q, 1));
         d.dots = a.template take<double>((size_t)nprob * d.dots_blocks * s * 2);
+        d.colsum = a.template take<double>((size_t)2 * ncol);
         d.beta1 = a.template take<double>(ncol);
         d.beta_cur = a.template take<double>(ncol);
         d.alpha = a.template take<double>(ncol);
@@ -250,7 +252,12 @@ struct Run {
 
     void configure(int rt_) {
         rt = rt_;
-        d.dots_blocks = std::min(64, std::max(1, (max_n + 255) / 256));
+        {   // ~8 rows per thread in the inner-product kernels
+            int ts = 1;
+            while (ts < s && ts < 64) ts <<= 1;
+            const int rows_per_pass = 256 / ts;
+            d.dots_blocks = std::min(1024, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
+        }
         const int rpb = rows_per_block();
         nrb = 0;
         for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rpb - 1) / rpb;
@@ -298,6 +305,7 @@ struct Run {
         HIPCHK(hipMemcpyAsync(poff, h_off.data(), nprob * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(po2, h_o2.data(), nprob * sizeof(float), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(ps2, h_s2.data(), nprob * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pscale, h_scale.data(), h_scale.size() * sizeof(double), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));  // host vectors are pageable and short-lived
         return CIQ_OK;
     }
@@ -315,6 +323,9 @@ struct Run {
         a.dp = dp;
         a.nsplit = nsplit;
         a.rt = rt;
+        a.ard = ard;
+        for (int k = 0; k < CIQ_MAX_D; ++k) a.scale[k] = h_scale[k];
+        a.pscale = pscale;
         a.n = h_n[0];
         a.o2 = h_o2d[0];
         a.s2 = h_s2d[0];
@@ -335,6 +346,7 @@ struct Run {
         // the state is reused scratch: clear `done` before the first kernel that reads it
         HIPCHK(launch_fill<int>(reinterpret_cast<int*>(d.st), sizeof(IterState) / sizeof(int), 0, st));
         HIPCHK(launch_dots<double>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
+        HIPCHK(launch_colsum(d, 1, st));
         HIPCHK(launch_scalar_init(d, st));
         if (Q > 0) {
             HIPCHK(launch_fill<double>(mbuf[0], (size_t)rows_total * s * Q, 0.0, st));
@@ -357,7 +369,9 @@ struct Run {
                 ++pending;
             }
             HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+            HIPCHK(launch_colsum(d, 0, st));
             HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+            HIPCHK(launch_colsum(d, 1, st));
             HIPCHK(launch_scalar(d, st));
             HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, q32,
                                          max_n, st));
@@ -442,6 +456,8 @@ int setup_points(Run<T>& r, const ciq_problem* probs, int dtype, hipStream_t st)
     for (int p = 0; p < r.nprob; ++p) {
         double scale[CIQ_MAX_D];
         point_scale(&probs[p], dtype, scale);
+        if (dtype != CIQ_F64)   // FP32 product scales coordinate differences instead
+            for (int k = 0; k < CIQ_MAX_D; ++k) scale[k] = 1.0;
         HIPCHK(launch_prep<T>(static_cast<const T*>(probs[p].x), probs[p].n, probs[p].d, r.dp, scale,
                               r.xh + (size_t)r.h_off[p] * r.dp, st));
     }
@@ -469,6 +485,16 @@ void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob, int dty
         r.h_s2[p] = (float)probs[p].noise;
         r.h_o2d[p] = probs[p].outputscale;
         r.h_s2d[p] = probs[p].noise;
+    }
+    r.h_scale.assign((size_t)nprob * CIQ_MAX_D, 0.0);
+    r.ard = 0;
+    for (int p = 0; p < nprob; ++p) {
+        double sc[CIQ_MAX_D];
+        point_scale(&probs[p], dtype, sc);
+        for (int k = 0; k < probs[p].d; ++k) {
+            r.h_scale[(size_t)p * CIQ_MAX_D + k] = sc[k];
+            if (sc[k] != sc[0]) r.ard = 1;
+        }
     }
     r.rows_total = off;
     r.max_n = maxn;
@@ -522,7 +548,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     const size_t off_after_xh = 0;
     (void)off_after_xh;
     Sizer szb;
-    szb.take<T>((size_t)main.rows_total * main.dp);
+    szb.take<double>((size_t)main.rows_total * main.dp);
     bnd.layout(szb, false);
     const size_t need = std::max(sz.off, szb.off) + 4096;
     void* base = nullptr;
@@ -532,7 +558,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     Carver cm(base);
     main.layout(cm, true);
     Carver cb(base);
-    bnd.xh = cb.take<T>((size_t)main.rows_total * main.dp);
+    bnd.xh = cb.take<double>((size_t)main.rows_total * main.dp);
     bnd.layout(cb, false);
     main.fill_dev();
     bnd.fill_dev();
@@ -858,7 +884,8 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     const int nsplit = mvm_pick_nsplit(dtype, nrb, p->n, s);
     // stream-ordered scratch: scaled points + FP64 split partials (the FP32
     // product accumulates in FP64; the last step rounds to the caller's type)
-    const size_t xbytes = ((size_t)p->n * dp * esz + 255) & ~size_t(255);
+    const size_t xbytes = ((size_t)p->n * dp * sizeof(double) + 255) & ~size_t(255);
+    (void)esz;
     const bool direct = (dtype == CIQ_F64 && nsplit == 1);
     const size_t ybytes = direct ? 0 : (size_t)nsplit * p->n * s * sizeof(double);
     void* buf = nullptr;
@@ -868,12 +895,14 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     }
     double scale[CIQ_MAX_D];
     point_scale(p, dtype, scale);
+    double ones[CIQ_MAX_D];
+    for (int k = 0; k < CIQ_MAX_D; ++k) ones[k] = 1.0;
     hipError_t e;
     if (dtype == CIQ_F64)
         e = launch_prep<double>(static_cast<const double*>(p->x), p->n, p->d, dp, scale, static_cast<double*>(buf),
                                 stream);
     else
-        e = launch_prep<float>(static_cast<const float*>(p->x), p->n, p->d, dp, scale, static_cast<float*>(buf),
+        e = launch_prep<float>(static_cast<const float*>(p->x), p->n, p->d, dp, ones, static_cast<double*>(buf),
                                stream);
     if (e != hipSuccess) return CIQ_EHIP;
     MvmArgs a{};
@@ -888,6 +917,12 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     a.dp = dp;
     a.nsplit = nsplit;
     a.rt = 2;
+    a.ard = 0;
+    for (int k = 0; k < CIQ_MAX_D; ++k) {
+        a.scale[k] = (k < p->d) ? scale[k] : 0.0;
+        if (k < p->d && scale[k] != scale[0]) a.ard = 1;
+    }
+    a.pscale = nullptr;
     a.n = p->n;
     a.o2 = p->outputscale;
     a.s2 = p->noise;

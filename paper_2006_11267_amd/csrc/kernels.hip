@@ -22,9 +22,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 
-// Kernel entry from the squared distance of pre-scaled points.
-//  RBF:      points scaled by sqrt(log2(e)/2)/l  ->  k = 2^{-r2} = exp(-r^2/2)
-//  Matern52: points scaled by sqrt(5)/l          ->  rho = sqrt5 r,
+// Kernel entry from the scaled squared distance r2 = sum_d (sc_d (x_d - x'_d))^2:
+//  RBF:      sc_d = sqrt(log2(e)/2)/l_d  ->  k = 2^{-r2} = exp(-r^2/2)
+//  Matern52: sc_d = sqrt(5)/l_d          ->  rho = sqrt5 r,
 //            k = (1 + rho + rho^2/3) 2^{-rho log2 e}
 template <int KERNEL>
 __device__ __forceinline__ float kfun32(float r2) {
@@ -50,179 +50,6 @@ __device__ __forceinline__ double kfun64(double r2) {
 }
 
 __device__ __forceinline__ int done_now(const int* done) { return done != nullptr && *done != 0; }
-
-// ----------------------------------------------------------------------------
-// FP32 kernel product on MFMA.
-//
-// Work decomposition: a block of 4 waves owns BM = 64*RT consecutive rows of
-// one problem and one of `nsplit` contiguous ranges of columns j of K. Wave w
-// owns rows [16*RT*w, 16*RT*(w+1)) of the block. Per 16 x 16 tile of K and
-// per 16 columns of V, four v_mfma_f32_16x16x4_f32 cover the 16 j's: in step
-// `st` lane l supplies A = K[i0 + l%16][j0 + 4*st + l/16] (computed in
-// registers from its own x_i and the staged x_j) and
-// B = V[j0 + 4*st + l/16][c0 + l%16] (from LDS); the accumulator holds
-// Y[i0 + 4*(l/16) + r][c0 + l%16], r = 0..3.
-//
-// Accumulation: the MFMA accumulates one staged chunk of BN columns of K in
-// FP32; each lane then adds its chunk sums into FP64 registers and restarts
-// the FP32 accumulator. A plain FP32 accumulation over all N/nsplit columns
-// loses ~sqrt(N) eps32 per output, and CIQ amplifies product errors by up to
-// kappa(K); with the FP64 running sums the products carry only the rounding
-// of the FP32 kernel entries and of short FP32 chunk sums.
-// ----------------------------------------------------------------------------
-template <int KERNEL, int DP, int NSB, int RT>
-__global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
-    constexpr int BM = 64 * RT;
-    constexpr int BN = 64;
-    constexpr int S16 = NSB * 16;
-    constexpr int VST = (NSB & 1) ? S16 : S16 + 16;  // LDS row stride: rows j, j+1 hit disjoint banks
-    constexpr int XE = BN * DP;                       // staged point floats per chunk
-    constexpr int XPT = (XE + 255) / 256;             // per thread
-    constexpr int VPT = BN * S16 / 256;               // staged V floats per thread
-    constexpr int VROWS = 256 / S16;                  // V rows covered by one pass of the block
-    __shared__ float xs[XE];
-    __shared__ float vs[BN * VST];
-
-    if (done_now(a.done)) return;
-    int n, off, rb;
-    double o2, s2;
-    if (a.wl != nullptr) {
-        const WorkItem wi = a.wl[blockIdx.x];
-        if (a.prob_done != nullptr && a.prob_done[wi.prob]) return;
-        n = a.pn[wi.prob];
-        off = a.poff[wi.prob];
-        rb = wi.rb;
-        o2 = a.po2[wi.prob];
-        s2 = a.ps2[wi.prob];
-    } else {
-        n = a.n;
-        off = 0;
-        rb = blockIdx.x;
-        o2 = a.o2;
-        s2 = a.s2;
-    }
-    const int split = blockIdx.y;
-    const float* __restrict__ xh = static_cast<const float*>(a.xh) + (long long)off * DP;
-    const float* __restrict__ v = static_cast<const float*>(a.v) + (long long)off * a.ldv;
-    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit + (long long)off * a.ldy;
-    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int row0 = rb * BM + wave * 16 * RT;
-
-    float xi[RT][DP];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-        const int i = row0 + rt * 16 + (lane & 15);
-#pragma unroll
-        for (int k = 0; k < DP; ++k) xi[rt][k] = (i < n) ? xh[(long long)i * DP + k] : 0.0f;
-    }
-
-    floatx4 acc[RT][NSB];
-    double accd[RT][NSB][4];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int sb = 0; sb < NSB; ++sb) {
-            acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
-        }
-
-    const int nchunk = (n + BN - 1) / BN;
-    const int c0 = (int)(((long long)split * nchunk) / a.nsplit);
-    const int c1 = (int)(((long long)(split + 1) * nchunk) / a.nsplit);
-
-    // register staging of the next chunk (loads in flight while the current
-    // chunk is computed); each thread owns fixed (row, column) slots
-    const int vr = tid / S16, vc = tid - (tid / S16) * S16;
-    const bool vcol_ok = vc < s;
-    float xreg[XPT], vreg[VPT];
-    auto fetch = [&](int c) {
-        const int j0 = c * BN;
-#pragma unroll
-        for (int k = 0; k < XPT; ++k) {
-            const int e = tid + 256 * k;
-            const int j = j0 + e / DP;
-            xreg[k] = (e < XE && j < n) ? xh[(long long)j0 * DP + e] : 0.0f;
-        }
-        const float* vp = v + (long long)(j0 + vr) * ldv + vc;
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-            const int j = j0 + vr + k * VROWS;
-            vreg[k] = (vcol_ok && j < n) ? vp[(long long)k * VROWS * ldv] : 0.0f;
-        }
-    };
-    if (c0 < c1) fetch(c0);
-
-    for (int c = c0; c < c1; ++c) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < XPT; ++k) {
-            const int e = tid + 256 * k;
-            if (e < XE) xs[e] = xreg[k];
-        }
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
-        __syncthreads();
-        if (c + 1 < c1) fetch(c + 1);
-#pragma unroll
-        for (int jb = 0; jb < BN / 16; ++jb) {
-#pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const int jl = jb * 16 + st * 4 + (lane >> 4);
-                float xj[DP];
-#pragma unroll
-                for (int k = 0; k < DP; ++k) xj[k] = xs[jl * DP + k];
-                float kv[RT];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    float r2 = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < DP; ++k) {
-                        const float dd = xi[rt][k] - xj[k];
-                        r2 = fmaf(dd, dd, r2);
-                    }
-                    kv[rt] = kfun32<KERNEL>(r2);
-                }
-#pragma unroll
-                for (int sb = 0; sb < NSB; ++sb) {
-                    const float bv = vs[jl * VST + sb * 16 + (lane & 15)];
-#pragma unroll
-                    for (int rt = 0; rt < RT; ++rt)
-                        acc[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[rt], bv, acc[rt][sb], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int sb = 0; sb < NSB; ++sb) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[rt][sb][r];
-                acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
-    }
-
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-#pragma unroll
-        for (int sb = 0; sb < NSB; ++sb) {
-            const int cc = sb * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;
-                if (i < n && cc < s) {
-                    double val = o2 * accd[rt][sb][r];
-                    if (split == 0) val = fma(s2, (double)v[(long long)i * ldv + cc], val);
-                    y[(long long)i * ldy + cc] = val;
-                }
-            }
-        }
-    }
-}
 
 // ----------------------------------------------------------------------------
 // FP64 kernel product (VALU). Block: 64 rows x 4 j-lanes; grid (row blocks,
@@ -295,41 +122,6 @@ __global__ __launch_bounds__(256) void mvm_f64_kernel(MvmArgs a) {
     }
 }
 
-template <int KERNEL, int DP, int NSB>
-hipError_t launch_f32_nsb(const MvmArgs& a, int grid_x, hipStream_t st) {
-    dim3 grid(grid_x, a.nsplit);
-    if (a.rt == 1 || NSB >= 8)
-        hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 1>), grid, dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 2>), grid, dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-template <int KERNEL, int DP>
-hipError_t launch_f32_dp(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
-    switch (nsb) {
-        case 1: return launch_f32_nsb<KERNEL, DP, 1>(a, grid_x, st);
-        case 2: return launch_f32_nsb<KERNEL, DP, 2>(a, grid_x, st);
-        case 3:
-        case 4: return launch_f32_nsb<KERNEL, DP, 4>(a, grid_x, st);
-        case 5: case 6: case 7:
-        case 8: return launch_f32_nsb<KERNEL, DP, 8>(a, grid_x, st);
-        default: return launch_f32_nsb<KERNEL, DP, 16>(a, grid_x, st);
-    }
-}
-
-template <int KERNEL>
-hipError_t launch_f32_k(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
-    switch (a.dp) {
-        case 4: return launch_f32_dp<KERNEL, 4>(a, nsb, grid_x, st);
-        case 6: return launch_f32_dp<KERNEL, 6>(a, nsb, grid_x, st);
-        case 8: return launch_f32_dp<KERNEL, 8>(a, nsb, grid_x, st);
-        case 10: return launch_f32_dp<KERNEL, 10>(a, nsb, grid_x, st);
-        case 12: return launch_f32_dp<KERNEL, 12>(a, nsb, grid_x, st);
-        default: return launch_f32_dp<KERNEL, 16>(a, nsb, grid_x, st);
-    }
-}
-
 template <int KERNEL, int DP>
 hipError_t launch_f64_dp(const MvmArgs& a, hipStream_t st) {
     constexpr int SC = 8;
@@ -399,8 +191,11 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
         g.v = static_cast<const float*>(a.v) + c0;
         g.y = static_cast<double*>(a.y) + c0;
         const int nsb = (g.s + 15) / 16;
-        const hipError_t e = a.kernel == CIQ_KERNEL_RBF ? launch_f32_k<CIQ_KERNEL_RBF>(g, nsb, a.nrb, st)
-                                                        : launch_f32_k<CIQ_KERNEL_MATERN52>(g, nsb, a.nrb, st);
+        hipError_t e;
+        if (a.kernel == CIQ_KERNEL_RBF)
+            e = a.ard ? launch_mvm_f32_rbf_ard(g, nsb, a.nrb, st) : launch_mvm_f32_rbf_iso(g, nsb, a.nrb, st);
+        else
+            e = a.ard ? launch_mvm_f32_m52_ard(g, nsb, a.nrb, st) : launch_mvm_f32_m52_iso(g, nsb, a.nrb, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -413,24 +208,24 @@ struct Scale16 {
     double v[CIQ_MAX_D];
 };
 
-template <typename T>
-__global__ void prep_kernel(const T* x, int n, int d, int dp, Scale16 sc, T* xh) {
+template <typename TI>
+__global__ void prep_kernel(const TI* x, int n, int d, int dp, Scale16 sc, double* xh) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)n * dp) return;
     const int i = (int)(e / dp), k = (int)(e - (long long)i * dp);
-    xh[e] = (k < d) ? (T)((double)x[(long long)i * d + k] * sc.v[k]) : (T)0;
+    xh[e] = (k < d) ? (double)x[(long long)i * d + k] * sc.v[k] : 0.0;
 }
 
-template <typename T>
-hipError_t launch_prep(const T* x, int n, int d, int dp, const double* scale, T* xh, hipStream_t st) {
+template <typename TI>
+hipError_t launch_prep(const TI* x, int n, int d, int dp, const double* scale, double* xh, hipStream_t st) {
     Scale16 sc;
     for (int k = 0; k < CIQ_MAX_D; ++k) sc.v[k] = (k < d) ? scale[k] : 0.0;
     const long long total = (long long)n * dp;
     const int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(prep_kernel<T>, dim3(blocks), dim3(256), 0, st, x, n, d, dp, sc, xh);
+    hipLaunchKernelGGL(prep_kernel<TI>, dim3(blocks), dim3(256), 0, st, x, n, d, dp, sc, xh);
     return hipGetLastError();
 }
-template hipError_t launch_prep<float>(const float*, int, int, int, const double*, float*, hipStream_t);
+template hipError_t launch_prep<float>(const float*, int, int, int, const double*, double*, hipStream_t);
 template hipError_t launch_prep<double>(const double*, int, int, int, const double*, double*, hipStream_t);
 
 // ----------------------------------------------------------------------------
@@ -476,37 +271,21 @@ __host__ __device__ inline int col_tile(int s) {
     return ts;
 }
 
-__device__ inline double sum_partials(const Dev& d, int p, int c, int k) {
-    double acc = 0.0;
-    for (int b = 0; b < d.dots_blocks; ++b) acc += d.dots[(((long long)p * d.dots_blocks + b) * d.s + c) * 2 + k];
-    return acc;
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void dots_kernel(Dev d, const T* y, long long ysplit, int nsplit,
                                                    const T* q, const T* qp, int phase) {
     __shared__ double sh[256];
-    __shared__ double s_alpha[64];
-    __shared__ double s_beta[64];
     if (d.st->done) return;
     const int TS = col_tile(d.s), RL = 256 / TS;
     const int p = blockIdx.z;
     const int n = d.n[p], off = d.row_off[p], s = d.s;
     const int cl = threadIdx.x % TS, rl = threadIdx.x / TS;
     const int c = blockIdx.y * TS + cl;
-    if (threadIdx.x < TS) {
-        double al = 0.0, bj = 0.0;
-        if (c < s && q != nullptr) {
-            bj = d.beta_cur[p * s + c];
-            if (phase == 1) al = sum_partials(d, p, c, 0);
-        }
-        s_alpha[threadIdx.x] = al;
-        s_beta[threadIdx.x] = bj;
-    }
-    __syncthreads();
-    const double al = s_alpha[cl], bj = s_beta[cl];
     double acc = 0.0;
     if (c < s) {
+        const int g = p * s + c;
+        const double bj = (q != nullptr) ? d.beta_cur[g] : 0.0;
+        const double al = (q != nullptr && phase == 1) ? d.colsum[g] : 0.0;
         for (int i = blockIdx.x * RL + rl; i < n; i += gridDim.x * RL) {
             const long long idx = (long long)(off + i) * s + c;
             double yv = (double)y[idx];
@@ -534,6 +313,30 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, const T* y, long long 
     }
 }
 
+// Column sums of the block partials, fixed order: colsum[k * ncol + g] =
+// sum_b dots[p][b][c][k]. Block: 64 columns x 4 lanes.
+__global__ __launch_bounds__(256) void colsum_kernel(Dev d, int k) {
+    __shared__ double sh[256];
+    if (d.st->done) return;
+    const int cl = threadIdx.x & 63, lane4 = threadIdx.x >> 6;
+    const int g = blockIdx.x * 64 + cl;
+    double acc = 0.0;
+    if (g < d.ncol) {
+        const int p = g / d.s, c = g - p * d.s;
+        const double* base = d.dots + ((long long)p * d.dots_blocks * d.s + c) * 2 + k;
+        for (int b = lane4; b < d.dots_blocks; b += 4) acc += base[(long long)b * d.s * 2];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (lane4 == 0 && g < d.ncol)
+        d.colsum[(long long)k * d.ncol + g] = sh[cl] + sh[64 + cl] + sh[128 + cl] + sh[192 + cl];
+}
+
+hipError_t launch_colsum(const Dev& d, int k, hipStream_t st) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((d.ncol + 63) / 64), dim3(256), 0, st, d, k);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q, const T* qp,
                        int phase, hipStream_t st) {
@@ -553,7 +356,7 @@ __global__ __launch_bounds__(1024) void scalar_init_kernel(Dev d) {
     __syncthreads();
     const int ncol = d.ncol, Q = d.Q;
     for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
-        const double b1 = sqrt(sum_partials(d, g / d.s, g % d.s, 1));
+        const double b1 = sqrt(d.colsum[(long long)d.ncol + g]);
         const bool ok = (b1 > 0.0) && isfinite(b1);
         d.beta1[g] = ok ? b1 : 0.0;
         d.beta_cur[g] = 0.0;
@@ -614,10 +417,9 @@ __global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
 
     for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
         if (!d.colactive[g]) continue;
-        const int p = g / s, c = g - p * s;
         const double bj = d.beta_cur[g];
-        double al = sum_partials(d, p, c, 0);
-        double bn = sqrt(sum_partials(d, p, c, 1));
+        double al = d.colsum[g];
+        double bn = sqrt(fmax(d.colsum[(long long)ncol + g], 0.0));
         // ||K q_j|| ~ sqrt(alpha^2 + beta_j^2 + beta_{j+1}^2) scales the breakdown test
         bool broke = !(bn > d.bd_rtol * sqrt(al * al + bj * bj + bn * bn));
         if (!isfinite(al) || !isfinite(bn)) {

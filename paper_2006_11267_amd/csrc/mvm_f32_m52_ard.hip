@@ -1,0 +1,8 @@
+// FP32 MFMA kernel product, CIQ_KERNEL_MATERN52, per-dimension lengthscale.
+#include "mvm_f32.h"
+
+namespace ciq {
+hipError_t launch_mvm_f32_m52_ard(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
+    return f32mvm::launch_f32_k<CIQ_KERNEL_MATERN52, true>(a, nsb, grid_x, st);
+}
+}  // namespace ciq
