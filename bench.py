@@ -5,7 +5,10 @@ One step = one full ciq_sqrt_mvm call on the Matern-5/2 workload (N = 50,000
 points in [0,1]^6, lengthscale 0.3, outputscale 1, noise 1e-3, S = 64 Gaussian
 right-hand sides, Q = 15, tol 1e-4): Lanczos eigenvalue bounds, HHT shifts,
 msMINRES to tolerance, weighted combine and the final product with K.
-Inputs are resident in device memory before the timed region.
+Inputs are resident in device memory before the timed region. The default
+path computes the kernel product on FP64 MFMA: at this conditioning
+(kappa ~ 2.5e6) FP32 products leave ~2e-4 relative error, above the 1e-4 the
+metric asks for.
 
 Prints ONE JSON line (metric, value, roofline, cpu_baseline, ...).
 """
@@ -22,7 +25,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix peaks
 METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
 
 
@@ -72,6 +75,9 @@ def main() -> int:
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--n", type=int, default=None, help="shrink N (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
+                    help="f64: FP64 MFMA product (meets 1e-4 at this conditioning); "
+                         "f32: FP32 MFMA product (~2e-4 at kappa 2.5e6)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -84,8 +90,9 @@ def main() -> int:
     wl = workloads.workload(2, n=args.n)
     p = wl.problems[0]
     dev = torch.device("cuda:0")
-    x = torch.from_numpy(p.x).to(dev)
-    b = torch.from_numpy(p.b).to(dev)
+    tdt = torch.float64 if args.precision == "f64" else torch.float32
+    x = torch.from_numpy(p.x).to(dev).to(tdt)        # inputs resident in HBM before timing
+    b = torch.from_numpy(p.b).to(dev).to(tdt)
     prob = ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise)
     n, s = p.b.shape
     q, tol = wl.q, wl.tol
@@ -121,6 +128,7 @@ def main() -> int:
     avg_ms = mvm_ms / max(mvm_n, 1)
     flops = 2.0 * n * n * s                 # algorithmic tile x V contraction per launch
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[args.precision]
 
     res = {
         "metric": METRIC,
@@ -133,7 +141,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {
             "workload": wl.name, "kernel": "matern52", "n": n, "d": p.d, "s": s, "q": q, "tol": tol,
@@ -142,9 +150,10 @@ def main() -> int:
             "lambda_max": info["lambda_max"], "mvm_per_step": info["mvm_count"],
         },
         "roofline": {
-            "bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
-            "kernel": "mvm_f32_kernel", "avg_ms": avg_ms, "launches": mvm_n,
+            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "kernel": "mvm_f64mfma_kernel" if args.precision == "f64" else "mvm_f32_kernel",
+            "avg_ms": avg_ms, "launches": mvm_n,
         },
     }
     if not args.no_cpu:

@@ -18,6 +18,7 @@ LIB = os.path.join(PKG, "libciq.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["mvm_f32_rbf_iso.hip", "mvm_f32_rbf_ard.hip", "mvm_f32_m52_iso.hip", "mvm_f32_m52_ard.hip",
+           "mvm_f64_rbf_iso.hip", "mvm_f64_rbf_ard.hip", "mvm_f64_m52_iso.hip", "mvm_f64_m52_ard.hip",
            "kernels.hip", "grad.hip", "elliptic.cpp", "host.cpp"]
 
 # Packed FP32 (v_pk_*_f32) is disabled for every device pass.

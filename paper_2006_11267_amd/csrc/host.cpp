@@ -108,10 +108,10 @@ struct Sizer {
     }
 };
 
-// Point padding: the FP32 product is instantiated for 4/6/8/10/12/16 dims, the
-// FP64 product and the gradient pass for 4/8/12/16.
+// Point padding: the products are instantiated for 4/6/8/10/12/16 dims, the
+// gradient pass (dtype < 0) for 4/8/12/16.
 int pad_dims(int d, int dtype) {
-    if (dtype != CIQ_F64 && dtype >= 0)
+    if (dtype >= 0)
         return d <= 4 ? 4 : d <= 6 ? 6 : d <= 8 ? 8 : d <= 10 ? 10 : d <= 12 ? 12 : 16;
     return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : 16;
 }
@@ -410,9 +410,9 @@ struct Run {
 // product's input type; the timed launches write only the partial buffer.
 template <typename T>
 int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
-    const int nsb = (std::min(r.s, 256) + 15) / 16;
-    if (r.dtype == CIQ_F64 || nsb >= 8) {
-        r.configure(r.dtype == CIQ_F64 ? 2 : 1);
+    const int nsb = (std::min(r.s, r.dtype == CIQ_F64 ? 64 : 128) + 15) / 16;
+    if (r.dtype != CIQ_F64 && nsb >= 8) {
+        r.configure(1);
         return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
     }
     int nlog = 0;
@@ -456,8 +456,7 @@ int setup_points(Run<T>& r, const ciq_problem* probs, int dtype, hipStream_t st)
     for (int p = 0; p < r.nprob; ++p) {
         double scale[CIQ_MAX_D];
         point_scale(&probs[p], dtype, scale);
-        if (dtype != CIQ_F64)   // FP32 product scales coordinate differences instead
-            for (int k = 0; k < CIQ_MAX_D; ++k) scale[k] = 1.0;
+        for (int k = 0; k < CIQ_MAX_D; ++k) scale[k] = 1.0;   // products scale differences
         HIPCHK(launch_prep<T>(static_cast<const T*>(probs[p].x), probs[p].n, probs[p].d, r.dp, scale,
                               r.xh + (size_t)r.h_off[p] * r.dp, st));
     }
@@ -886,7 +885,7 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     // product accumulates in FP64; the last step rounds to the caller's type)
     const size_t xbytes = ((size_t)p->n * dp * sizeof(double) + 255) & ~size_t(255);
     (void)esz;
-    const bool direct = (dtype == CIQ_F64 && nsplit == 1);
+    const bool direct = (dtype == CIQ_F64 && nsplit == 1 && s <= 64);
     const size_t ybytes = direct ? 0 : (size_t)nsplit * p->n * s * sizeof(double);
     void* buf = nullptr;
     if (hipMallocAsync(&buf, xbytes + ybytes, stream) != hipSuccess) {
@@ -899,7 +898,7 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     for (int k = 0; k < CIQ_MAX_D; ++k) ones[k] = 1.0;
     hipError_t e;
     if (dtype == CIQ_F64)
-        e = launch_prep<double>(static_cast<const double*>(p->x), p->n, p->d, dp, scale, static_cast<double*>(buf),
+        e = launch_prep<double>(static_cast<const double*>(p->x), p->n, p->d, dp, ones, static_cast<double*>(buf),
                                 stream);
     else
         e = launch_prep<float>(static_cast<const float*>(p->x), p->n, p->d, dp, ones, static_cast<double*>(buf),

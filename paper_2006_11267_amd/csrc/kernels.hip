@@ -1,10 +1,8 @@
 // Device kernels of libciq (gfx950).
 //
 //  * Kernel product Y = o^2 k(X, X) V + sigma^2 V without storing K (Sec. 3.2,
-//    Property 1): points are staged through LDS, each lane evaluates the
-//    kernel entries that form its MFMA A-operand directly in registers, and the
-//    tile x V contraction runs on v_mfma_f32_16x16x4_f32 (FP32) with FP32
-//    accumulation. The FP64 path uses plain VALU FMA.
+//    Property 1): the MFMA kernels live in mvm_mfma.h (FP32 and FP64 paths);
+//    this file holds their dispatch (column groups, split of the j range).
 //  * msMINRES step (Appendix C, Alg. S4): one reduction kernel for the six
 //    FP64 inner products a Lanczos step needs, one single-block FP64 scalar
 //    stage (Lanczos alpha/beta, per-shift Givens QR, stopping rule), and one
@@ -18,135 +16,11 @@ namespace ciq {
 
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-constexpr float kLog2e = 1.4426950408889634f;
-
-// Kernel entry from the scaled squared distance r2 = sum_d (sc_d (x_d - x'_d))^2:
-//  RBF:      sc_d = sqrt(log2(e)/2)/l_d  ->  k = 2^{-r2} = exp(-r^2/2)
-//  Matern52: sc_d = sqrt(5)/l_d          ->  rho = sqrt5 r,
-//            k = (1 + rho + rho^2/3) 2^{-rho log2 e}
-template <int KERNEL>
-__device__ __forceinline__ float kfun32(float r2) {
-    if constexpr (KERNEL == CIQ_KERNEL_RBF) {
-        return __builtin_amdgcn_exp2f(-r2);
-    } else {
-        const float rho = __builtin_amdgcn_sqrtf(r2);
-        const float e = __builtin_amdgcn_exp2f(-kLog2e * rho);
-        return fmaf(rho, fmaf(rho, 1.0f / 3.0f, 1.0f), 1.0f) * e;
-    }
-}
-
-//  RBF:      points scaled by 1/l       ->  k = exp(-r2 / 2)
-//  Matern52: points scaled by sqrt5/l   ->  rho = sqrt(r2), k = (1 + rho + rho^2/3) exp(-rho)
-template <int KERNEL>
-__device__ __forceinline__ double kfun64(double r2) {
-    if constexpr (KERNEL == CIQ_KERNEL_RBF) {
-        return exp(-0.5 * r2);
-    } else {
-        const double rho = sqrt(r2);
-        return (1.0 + rho + rho * rho * (1.0 / 3.0)) * exp(-rho);
-    }
-}
-
-__device__ __forceinline__ int done_now(const int* done) { return done != nullptr && *done != 0; }
-
-// ----------------------------------------------------------------------------
-// FP64 kernel product (VALU). Block: 64 rows x 4 j-lanes; grid (row blocks,
-// nsplit, column groups of SC). Each thread accumulates SC columns over its
-// j-lane, the 4 j-lanes are summed in LDS in a fixed order.
-// ----------------------------------------------------------------------------
-template <int KERNEL, int DP, int SC>
-__global__ __launch_bounds__(256) void mvm_f64_kernel(MvmArgs a) {
-    constexpr int BN = 64;
-    __shared__ double xs[BN * DP];
-    __shared__ double vs[BN * SC];
-    __shared__ double red[4 * 64 * SC];
-    if (done_now(a.done)) return;
-    const int n = a.n;
-    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
-    const double* __restrict__ xh = static_cast<const double*>(a.xh);
-    const double* __restrict__ v = static_cast<const double*>(a.v);
-    const int split = blockIdx.y;
-    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
-    const int il = threadIdx.x & 63, jl = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + il;
-    const int cg = blockIdx.z * SC;
-    double xi[DP];
-#pragma unroll
-    for (int k = 0; k < DP; ++k) xi[k] = (i < n) ? xh[(long long)i * DP + k] : 0.0;
-    double acc[SC];
-#pragma unroll
-    for (int c = 0; c < SC; ++c) acc[c] = 0.0;
-    const int nchunk = (n + BN - 1) / BN;
-    const int c0 = (int)(((long long)split * nchunk) / a.nsplit);
-    const int c1 = (int)(((long long)(split + 1) * nchunk) / a.nsplit);
-    for (int ch = c0; ch < c1; ++ch) {
-        const int j0 = ch * BN;
-        __syncthreads();
-        for (int e = threadIdx.x; e < BN * DP; e += 256) {
-            const int j = j0 + e / DP;
-            xs[e] = (j < n) ? xh[(long long)j0 * DP + e] : 0.0;
-        }
-        for (int e = threadIdx.x; e < BN * SC; e += 256) {
-            const int jj = e / SC, cc = e - jj * SC;
-            const int j = j0 + jj;
-            vs[e] = (j < n && cg + cc < s) ? v[(long long)j * ldv + cg + cc] : 0.0;
-        }
-        __syncthreads();
-        for (int jj = jl; jj < BN; jj += 4) {
-            double r2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < DP; ++k) {
-                const double dd = xi[k] - xs[jj * DP + k];
-                r2 = fma(dd, dd, r2);
-            }
-            const double kij = kfun64<KERNEL>(r2);
-#pragma unroll
-            for (int c = 0; c < SC; ++c) acc[c] = fma(kij, vs[jj * SC + c], acc[c]);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < SC; ++c) red[(jl * 64 + il) * SC + c] = acc[c];
-    __syncthreads();
-    if (jl == 0 && i < n) {
-#pragma unroll
-        for (int c = 0; c < SC; ++c) {
-            if (cg + c >= s) break;
-            double val = red[(0 * 64 + il) * SC + c] + red[(1 * 64 + il) * SC + c] +
-                         red[(2 * 64 + il) * SC + c] + red[(3 * 64 + il) * SC + c];
-            val *= a.o2;
-            if (split == 0) val = fma(a.s2, v[(long long)i * ldv + cg + c], val);
-            y[(long long)i * ldy + cg + c] = val;
-        }
-    }
-}
-
-template <int KERNEL, int DP>
-hipError_t launch_f64_dp(const MvmArgs& a, hipStream_t st) {
-    constexpr int SC = 8;
-    dim3 grid((a.n + 63) / 64, a.nsplit, (a.s + SC - 1) / SC);
-    hipLaunchKernelGGL((mvm_f64_kernel<KERNEL, DP, SC>), grid, dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-template <int KERNEL>
-hipError_t launch_f64_k(const MvmArgs& a, hipStream_t st) {
-    switch (a.dp) {
-        case 4: return launch_f64_dp<KERNEL, 4>(a, st);
-        case 6:
-        case 8: return launch_f64_dp<KERNEL, 8>(a, st);
-        case 10:
-        case 12: return launch_f64_dp<KERNEL, 12>(a, st);
-        default: return launch_f64_dp<KERNEL, 16>(a, st);
-    }
-}
-
 }  // namespace
 
 int mvm_rows_per_block(int dtype, int s, int rt) {
-    if (dtype == CIQ_F64) return 64;
-    const int nsb = (s > 256 ? 256 : s + 15) / 16;
+    if (dtype == CIQ_F64) return 64 * rt;            // FP64 MFMA: column groups of <= 64
+    const int nsb = (s > 128 ? 128 : s + 15) / 16;
     return (nsb <= 4 && rt == 2) ? 128 : 64;
 }
 
@@ -154,13 +28,11 @@ int mvm_rows_per_block(int dtype, int s, int rt) {
 // resident slots (256 CUs x blocks resident per CU, set by the kernel's
 // register use) with the least idle tail.
 int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s) {
-    int per_cu = 4;
-    if (dtype != CIQ_F64) {
-        const int nsb = (s > 256 ? 256 : s + 15) / 16;
-        per_cu = nsb <= 2 ? 4 : nsb <= 8 ? 2 : 1;
-    }
+    const int cap = (dtype == CIQ_F64) ? 64 : 128;
+    const int nsb = (s > cap ? cap : s + 15) / 16;
+    const int per_cu = nsb <= 2 ? 4 : 2;
     const int slots = 256 * per_cu;
-    const int max_split = (dtype == CIQ_F64) ? 16 : 8;
+    const int max_split = 8;
     int best = 1;
     double best_eff = 0.0;
     for (int sp = 1; sp <= max_split; ++sp) {
@@ -179,23 +51,28 @@ int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s) {
 }
 
 hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
-    if (dtype == CIQ_F64) {
-        return a.kernel == CIQ_KERNEL_RBF ? launch_f64_k<CIQ_KERNEL_RBF>(a, st)
-                                          : launch_f64_k<CIQ_KERNEL_MATERN52>(a, st);
-    }
-    // the MFMA kernel holds at most 16 column blocks (256 columns) in
-    // accumulators; wider right-hand sides run as column groups
-    for (int c0 = 0; c0 < a.s; c0 += 256) {
+    // Accumulators hold at most 8 (FP32) / 4 (FP64) column blocks of 16; wider
+    // right-hand sides run as column groups, each regenerating its entries.
+    const int cap = (dtype == CIQ_F64) ? 64 : 128;
+    for (int c0 = 0; c0 < a.s; c0 += cap) {
         MvmArgs g = a;
-        g.s = (a.s - c0 < 256) ? a.s - c0 : 256;
-        g.v = static_cast<const float*>(a.v) + c0;
+        g.s = (a.s - c0 < cap) ? a.s - c0 : cap;
         g.y = static_cast<double*>(a.y) + c0;
         const int nsb = (g.s + 15) / 16;
         hipError_t e;
-        if (a.kernel == CIQ_KERNEL_RBF)
-            e = a.ard ? launch_mvm_f32_rbf_ard(g, nsb, a.nrb, st) : launch_mvm_f32_rbf_iso(g, nsb, a.nrb, st);
-        else
-            e = a.ard ? launch_mvm_f32_m52_ard(g, nsb, a.nrb, st) : launch_mvm_f32_m52_iso(g, nsb, a.nrb, st);
+        if (dtype == CIQ_F64) {
+            g.v = static_cast<const double*>(a.v) + c0;
+            if (a.kernel == CIQ_KERNEL_RBF)
+                e = a.ard ? launch_mvm_f64_rbf_ard(g, nsb, a.nrb, st) : launch_mvm_f64_rbf_iso(g, nsb, a.nrb, st);
+            else
+                e = a.ard ? launch_mvm_f64_m52_ard(g, nsb, a.nrb, st) : launch_mvm_f64_m52_iso(g, nsb, a.nrb, st);
+        } else {
+            g.v = static_cast<const float*>(a.v) + c0;
+            if (a.kernel == CIQ_KERNEL_RBF)
+                e = a.ard ? launch_mvm_f32_rbf_ard(g, nsb, a.nrb, st) : launch_mvm_f32_rbf_iso(g, nsb, a.nrb, st);
+            else
+                e = a.ard ? launch_mvm_f32_m52_ard(g, nsb, a.nrb, st) : launch_mvm_f32_m52_iso(g, nsb, a.nrb, st);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

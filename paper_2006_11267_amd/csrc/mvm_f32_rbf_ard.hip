@@ -1,5 +1,5 @@
 // FP32 MFMA kernel product, CIQ_KERNEL_RBF, per-dimension lengthscale.
-#include "mvm_f32.h"
+#include "mvm_mfma.h"
 
 namespace ciq {
 hipError_t launch_mvm_f32_rbf_ard(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {

@@ -1,0 +1,8 @@
+// FP64 MFMA kernel product, CIQ_KERNEL_RBF, isotropic lengthscale.
+#include "mvm_mfma.h"
+
+namespace ciq {
+hipError_t launch_mvm_f64_rbf_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
+    return f32mvm::launch_f64m_k<CIQ_KERNEL_RBF, false>(a, nsb, grid_x, st);
+}
+}  // namespace ciq

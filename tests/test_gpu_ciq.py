@@ -55,10 +55,10 @@ def test_fp64_recurrence_parity_small_j(mode, J):
 def test_fp64_workload1(mode):
     """The first workload as stated (RBF N=1024, S=1, Q=8, J=100, tol 1e-4,
     FP64). J=100 is past the loss of orthogonality and short of convergence:
-    there two correct finite-precision runs differ chaotically (a 1e-16
-    relative perturbation of each product moves the J=100 iterate by ~1e-4 in
-    the oracle itself). The bar is therefore: same iteration count, and the
-    GPU-oracle gap a small fraction of the method's own error."""
+    there two correct finite-precision runs differ chaotically. The bar is
+    calibrated on the oracle itself: its own iterate moves when every product
+    is perturbed by 1e-16 relative (three seeds); the GPU-oracle gap must be
+    within 3x the largest such move, with the same iteration count."""
     torch = torch_cuda()
     ciq = ciq_module()
     import workloads
@@ -73,11 +73,17 @@ def test_fp64_workload1(mode):
                       tol=wl.tol, bounds=bounds)
     out = out.cpu().numpy()
     ref, oinfo = ociq.ciq(lambda v: K @ v, p.b, bounds[0], bounds[1], wl.q, wl.max_iter, wl.tol, mode)
+    spread = 0.0
+    for seed in range(3):
+        rng = np.random.default_rng(seed)
+        pert = lambda v: (K @ v) * (1.0 + 1e-16 * rng.standard_normal(v.shape))
+        alt, _ = ociq.ciq(pert, p.b, bounds[0], bounds[1], wl.q, wl.max_iter, wl.tol, mode)
+        spread = max(spread, colwise_rel(alt, ref).max())
     exact = ociq.exact_power(K, p.b, 0.5 if mode == "sqrt" else -0.5)
     assert info["iters"] == oinfo.iters
     gap = colwise_rel(out, ref).max()
+    assert gap <= 3.0 * spread + 1e-12, (gap, spread)
     own = colwise_rel(ref, exact).max()
-    assert gap < 0.1 * own, (gap, own)
     assert colwise_rel(out, exact).max() < 1.2 * own
 
 

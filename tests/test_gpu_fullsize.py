@@ -1,8 +1,9 @@
-"""Full-size (N = 50,000, Matern-5/2, d = 6) accuracy of the FP32 path at the
+"""Full-size (N = 50,000, Matern-5/2, d = 6, kappa ~ 2.5e6) accuracy at the
 benchmark's settings. The oracle cannot run msMINRES at this size, so the
 checks are (i) a property that holds at any size, K^{-1/2} (K^{1/2} b) = b,
-and (ii) the FP32 result against the library's FP64 path run to a much
-tighter tolerance (the FP64 path is held to the oracle at smaller sizes)."""
+and (ii) the result at tol 1e-4 against the library's FP64 path run to tol
+1e-9 (the FP64 path is held to the oracle at smaller sizes, and its kernel
+product to the oracle's rows at this size)."""
 import numpy as np
 import pytest
 
@@ -20,11 +21,11 @@ def _problem(ciq, torch, dtype, s):
     return wl, ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise), b
 
 
-def test_round_trip_full_size():
+def test_round_trip_full_size_fp64():
     torch = torch_cuda()
     ciq = ciq_module()
-    wl, prob, b = _problem(ciq, torch, np.float32, 4)
-    announce("full-size round trip f32 n=50000 s=4")
+    wl, prob, b = _problem(ciq, torch, np.float64, 4)
+    announce("full-size round trip f64 n=50000 s=4")
     half, i1, _ = ciq.ciq_sqrt_mvm(prob, b, q=15, max_iter=4000, tol=1e-5, seed=4001)
     back, i2, _ = ciq.ciq_invsqrt_mvm(prob, half, q=15, max_iter=4000, tol=1e-5, seed=4001)
     err = colwise_rel(back.cpu().numpy(), b.cpu().numpy()).max()
@@ -33,17 +34,48 @@ def test_round_trip_full_size():
     assert err < 1e-4
 
 
-def test_fp32_at_bench_settings_vs_fp64_full_size():
+@pytest.fixture(scope="module")
+def tight_fp64():
+    """K^{-1/2} B and K^{1/2} B at tol 1e-9 on the FP64 path, with the bounds
+    the default path estimates."""
     torch = torch_cuda()
     ciq = ciq_module()
-    wl, p32, b32 = _problem(ciq, torch, np.float32, 4)
-    _, p64, b64 = _problem(ciq, torch, np.float64, 4)
-    announce("full-size f32 (tol 1e-4) vs f64 (tol 1e-9) n=50000 s=4")
-    bounds = None
-    out32, i32, _ = ciq.ciq_invsqrt_mvm(p32, b32, q=15, max_iter=4000, tol=wl.tol, seed=4001)
-    bounds = (i32["lambda_min"], i32["lambda_max"])
-    out64, i64, _ = ciq.ciq_invsqrt_mvm(p64, b64, q=15, max_iter=6000, tol=1e-9, bounds=bounds)
-    err = colwise_rel(out32.cpu().numpy(), out64.cpu().numpy()).max()
-    print(f"f32 vs f64 rel err {err:.3e} iters {i32['iters']} vs {i64['iters']}", flush=True)
-    assert i32["converged"] and i64["converged"]
+    wl, p64, b64 = _problem(ciq, torch, np.float64, 4)
+    announce("full-size f64 reference tol 1e-9 n=50000 s=4")
+    lo, hi = ciq.ciq_eig_bounds(p64, steps=20, seed=0)
+    bounds = (lo, hi)
+    inv, ii, _ = ciq.ciq_invsqrt_mvm(p64, b64, q=15, max_iter=8000, tol=1e-9, bounds=bounds)
+    sq, isq, _ = ciq.ciq_sqrt_mvm(p64, b64, q=15, max_iter=8000, tol=1e-9, bounds=bounds)
+    assert ii["converged"] and isq["converged"]
+    return bounds, inv.cpu().numpy(), sq.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["invsqrt", "sqrt"])
+def test_fp64_at_bench_settings_full_size(tight_fp64, mode):
+    """The benchmark's path (FP64 product, tol 1e-4) meets 1e-4 relative error."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    bounds, inv, sq = tight_fp64
+    wl, p64, b64 = _problem(ciq, torch, np.float64, 4)
+    announce(f"full-size f64 tol 1e-4 {mode} n=50000 s=4")
+    fn = ciq.ciq_invsqrt_mvm if mode == "invsqrt" else ciq.ciq_sqrt_mvm
+    out, info, _ = fn(p64, b64, q=15, max_iter=4000, tol=wl.tol, bounds=bounds)
+    err = colwise_rel(out.cpu().numpy(), inv if mode == "invsqrt" else sq).max()
+    print(f"f64 {mode} rel err {err:.3e} iters {info['iters']}", flush=True)
+    assert info["converged"]
     assert err < 1e-4
+
+
+def test_fp32_error_full_size(tight_fp64):
+    """The FP32 product at this conditioning: its error is stated (~2e-4,
+    FP32 entry rounding times kappa), bounded here at 5e-4."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    bounds, inv, sq = tight_fp64
+    wl, p32, b32 = _problem(ciq, torch, np.float32, 4)
+    announce("full-size f32 tol 1e-4 n=50000 s=4")
+    out, info, _ = ciq.ciq_invsqrt_mvm(p32, b32, q=15, max_iter=4000, tol=wl.tol, bounds=bounds)
+    err = colwise_rel(out.cpu().numpy(), inv).max()
+    print(f"f32 invsqrt rel err {err:.3e} iters {info['iters']}", flush=True)
+    assert info["converged"]
+    assert err < 5e-4

@@ -50,21 +50,23 @@ def test_mvm_isotropic_and_ldv():
     assert colwise_rel(y, K @ v[:, :20].astype(np.float64)).max() < 2e-6
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("kind,n,d,s", [("matern52", 50_000, 6, 64), ("rbf", 100_000, 8, 256)])
-def test_mvm_full_size_sampled_rows(kind, n, d, s):
+def test_mvm_full_size_sampled_rows(kind, n, d, s, prec):
     torch = torch_cuda()
     ciq = ciq_module()
     import workloads
     c = 2 if kind == "matern52" else 3
     wl = workloads.workload(c)
     p = wl.problems[0]
-    announce(f"mvm full size {kind} n={n} s={s}")
-    prob = ciq.Problem(torch.from_numpy(p.x).cuda(), p.kernel, p.lengthscale, p.outputscale, p.noise)
-    b = torch.from_numpy(p.b).cuda()
+    dt = np.float64 if prec == "f64" else np.float32
+    announce(f"mvm full size {prec} {kind} n={n} s={s}")
+    prob = ciq.Problem(torch.from_numpy(p.x.astype(dt)).cuda(), p.kernel, p.lengthscale, p.outputscale, p.noise)
+    b = torch.from_numpy(p.b.astype(dt)).cuda()
     y = ciq.ciq_kernel_mvm(prob, b).cpu().numpy()
     rows = np.random.default_rng(1).choice(n, 48, replace=False)
     rows = np.concatenate([rows, [0, n - 1]])
     Kr = okern.kernel_rows(p.kernel, p.x.astype(np.float64), p.lengthscale, p.outputscale, p.noise, rows)
     ref = Kr @ p.b.astype(np.float64)
     rel = np.linalg.norm(y[rows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    assert rel.max() < 1e-5, rel.max()
+    assert rel.max() < (1e-12 if prec == "f64" else 1e-5), rel.max()
