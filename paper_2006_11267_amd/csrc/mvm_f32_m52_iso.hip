@@ -3,6 +3,6 @@
 
 namespace ciq {
 hipError_t launch_mvm_f32_m52_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) {
-    return f32mvm::launch_f32_k<CIQ_KERNEL_MATERN52, false>(a, nsb, grid_x, st);
+    return mfma::launch_f32_k<CIQ_KERNEL_MATERN52, false>(a, nsb, grid_x, st);
 }
 }  // namespace ciq

@@ -7,7 +7,7 @@
 #include "ciq_internal.h"
 
 namespace ciq {
-namespace f32mvm {
+namespace mfma {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -30,29 +30,47 @@ __device__ __forceinline__ float kfun32(float r2) {
 
 __device__ __forceinline__ int done_now(const int* done) { return done != nullptr && *done != 0; }
 
-// e^{-y} for y >= 0 in FP64 (a few ulp).
+// e^{-y} for y >= 0 in FP64 (within 1 ulp). e^{-y} = 2^n e^g with
+// n = round(-y / ln2) and g = -y - n ln2, ln2 split in two parts (Cody-Waite)
+// so that g carries no reduction error; |g| <= ln2/2. e^g is a degree-11
+// polynomial fitted by the Remez exchange algorithm to minimise the maximum
+// relative error on [-ln2/2, ln2/2] (3e-18 before rounding the coefficients;
+// 1.6e-16 overall, checked in extended precision).
 __device__ __forceinline__ double exp_neg(double y) {
-    // e^{-y} = 2^n e^g, n = round(-y / ln2), g = -y - n ln2 with ln2 split in
-    // two parts (Cody-Waite) so g carries no reduction error; |g| <= ln2/2, and
-    // the Taylor polynomial of degree 13 leaves < 1e-17 relative truncation.
     const double nf = rint(-y * 1.4426950408889634074);
     double g = fma(-nf, 6.93147180559945286227e-01, -y);
     g = fma(-nf, 2.31904681384629955842e-17, g);
-    double p = 1.6059043836821613e-10;                // 1/13!
-    p = fma(p, g, 2.0876756987868099e-9);             // 1/12!
-    p = fma(p, g, 2.5052108385441720e-8);             // 1/11!
-    p = fma(p, g, 2.7557319223985891e-7);             // 1/10!
-    p = fma(p, g, 2.7557319223985893e-6);             // 1/9!
-    p = fma(p, g, 2.4801587301587302e-5);             // 1/8!
-    p = fma(p, g, 1.9841269841269841e-4);             // 1/7!
-    p = fma(p, g, 1.3888888888888889e-3);             // 1/6!
-    p = fma(p, g, 8.3333333333333333e-3);             // 1/5!
-    p = fma(p, g, 4.1666666666666667e-2);             // 1/4!
-    p = fma(p, g, 1.6666666666666667e-1);             // 1/3!
-    p = fma(p, g, 0.5);
+    double p = 2.4994304884817207e-08;
+    p = fma(p, g, 2.7632293279459877e-07);
+    p = fma(p, g, 2.7557622530872255e-06);
+    p = fma(p, g, 2.4801486521427463e-05);
+    p = fma(p, g, 1.9841269432679237e-04);
+    p = fma(p, g, 1.3888888951223987e-03);
+    p = fma(p, g, 8.33333333355927e-03);
+    p = fma(p, g, 4.166666666649277e-02);
+    p = fma(p, g, 1.6666666666666170e-01);
+    p = fma(p, g, 5.0000000000000180e-01);
     p = fma(p, g, 1.0);
     p = fma(p, g, 1.0);
     return ldexp(p, (int)fmax(nf, -1100.0));
+}
+
+// sqrt(x) for x >= 0 in FP64: hardware reciprocal square root, one
+// Goldschmidt step for (sqrt x, 1/(2 sqrt x)) and two Newton corrections of
+// the root. Inputs are clamped to 1e-200 so no scaling for subnormals or a
+// zero special case is needed: the result for x = 0 is 1e-100, which leaves
+// the Matern entry at exactly 1 in FP64.
+__device__ __forceinline__ double sqrt64(double x) {
+    x = fmax(x, 1e-200);
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
 }
 
 // FP64 kernel entry from the scaled squared distance r2:
@@ -64,8 +82,8 @@ __device__ __forceinline__ double kentry64(double r2) {
     if constexpr (KERNEL == CIQ_KERNEL_RBF) {
         return exp_neg(0.5 * r2);
     } else {
-        const double rho = sqrt(r2);
-        return fma(rho, fma(rho, 1.0 / 3.0, 1.0), 1.0) * exp_neg(rho);
+        const double rho = sqrt64(r2);
+        return (fma(r2, 1.0 / 3.0, 1.0) + rho) * exp_neg(rho);
     }
 }
 
@@ -487,5 +505,5 @@ hipError_t launch_f64m_k(const MvmArgs& a, int nsb, int grid_x, hipStream_t st) 
     }
 }
 
-}  // namespace f32mvm
+}  // namespace mfma
 }  // namespace ciq
