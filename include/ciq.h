@@ -63,6 +63,10 @@ extern "C" {
 #define CIQ_INVSQRT 0
 #define CIQ_SQRT    1
 
+#define CIQ_CACHE_AUTO 0   /* keep K resident when it fits (see ciq_opts.kernel_cache) */
+#define CIQ_CACHE_OFF  1   /* evaluate kernel entries in every product                */
+#define CIQ_CACHE_ON   2   /* always keep K resident (CIQ_ENOMEM if it does not fit)  */
+
 #define CIQ_MAX_Q   64   /* quadrature points                                       */
 #define CIQ_MAX_D   16   /* input dimensions                                        */
 
@@ -92,7 +96,18 @@ typedef struct ciq_opts {
     int32_t check_every;       /* iterations between host convergence polls (0: auto) */
     int32_t profile;           /* 1: time every kernel-product launch of the msMINRES
                                   loop with HIP events on `stream` (ciq_info.mvm_ms) */
-    int32_t reserved[6];
+    int32_t kernel_cache;      /* CIQ_CACHE_*. Single-problem CIQ_F64 solves may write
+                                  the unit-scale entries k(x_i, x_j) once per call
+                                  into a device buffer of kcache bytes
+                                  (ceil(n/128)*128 x ceil(n/64)*64 doubles, 20 GB at
+                                  n = 50,000) and stream them in every product
+                                  instead of re-evaluating them; the buffer is
+                                  allocated and freed inside the call. Results are
+                                  the same products up to summation order. Other
+                                  dtypes and the batched call ignore this field.  */
+    int32_t cache_budget_mib;  /* CIQ_CACHE_AUTO: largest matrix kept, in MiB
+                                  (0: half of the free device memory at the call) */
+    int32_t reserved[4];
 } ciq_opts;
 
 /* Per-call report (host). Valid when the call returned CIQ_OK. */
@@ -109,7 +124,7 @@ typedef struct ciq_info {
     double mvm_ms;             /* opts.profile: summed device time of the timed
                                   kernel-product launches (ms), else 0             */
     int32_t mvm_timed;         /* number of launches in mvm_ms                     */
-    int32_t reserved;
+    int32_t kernel_cached;     /* 1 if the products streamed a resident K           */
 } ciq_info;
 
 /* Library version (major*10000 + minor*100 + patch). */

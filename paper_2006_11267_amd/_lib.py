@@ -15,6 +15,8 @@ CIQ_OK, CIQ_EINVAL, CIQ_ENOMEM, CIQ_EHIP, CIQ_ENOTSUP, CIQ_ENUMERIC = range(6)
 CIQ_KERNEL_RBF, CIQ_KERNEL_MATERN52 = 0, 1
 CIQ_F64, CIQ_F32, CIQ_BF16X3, CIQ_F16X3 = 0, 1, 2, 3
 CIQ_INVSQRT, CIQ_SQRT = 0, 1
+CIQ_CACHE_AUTO, CIQ_CACHE_OFF, CIQ_CACHE_ON = 0, 1, 2
+CACHE_MODES = {"auto": CIQ_CACHE_AUTO, "off": CIQ_CACHE_OFF, "on": CIQ_CACHE_ON}
 CIQ_MAX_Q = 64
 CIQ_MAX_D = 16
 
@@ -47,7 +49,9 @@ class ciq_opts(ctypes.Structure):
         ("lambda_max", ctypes.c_double),
         ("check_every", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("kernel_cache", ctypes.c_int32),
+        ("cache_budget_mib", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -64,7 +68,7 @@ class ciq_info(ctypes.Structure):
         ("w", ctypes.c_double * CIQ_MAX_Q),
         ("mvm_ms", ctypes.c_double),
         ("mvm_timed", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("kernel_cached", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -81,6 +85,7 @@ class ciq_info(ctypes.Structure):
             "w": np.array(self.w[:q]),
             "mvm_ms": self.mvm_ms,
             "mvm_timed": self.mvm_timed,
+            "kernel_cached": bool(self.kernel_cached),
         }
 
 

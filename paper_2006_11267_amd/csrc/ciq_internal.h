@@ -100,7 +100,26 @@ struct MvmArgs {
     const float* ps2;        // [nprob]
     const int* prob_done;    // [nprob] or nullptr
     const int* done;         // global done flag or nullptr
+    // resident kernel matrix (single FP64 problem): operand-tiled unit-scale
+    // entries, see mvm_cache.hip; nullptr = evaluate entries on the fly
+    const double* kt;
+    long long njs;           // padded columns / 4
 };
+
+// Build pass of the resident kernel matrix (mvm_cache.hip).
+struct KBuildArgs {
+    const double* xh;        // n x dp FP64 points (raw coordinates)
+    double scale[CIQ_MAX_D]; // per-dimension scale of coordinate differences
+    int n, dp, kernel, ard;
+    int nchunk;              // padded columns / 64
+    long long njs;           // padded columns / 4
+    double* kt;              // kcache_rows(n) x kcache_cols(n) doubles
+};
+size_t kcache_rows(int n);
+size_t kcache_cols(int n);
+size_t kcache_bytes(int n);
+hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st);
+hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st);
 
 // ---- launchers (kernels.hip, mvm_f32_*.hip) ---------------------------------
 hipError_t launch_mvm_f32_rbf_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);

@@ -123,9 +123,10 @@ int pad_dims(int d, int dtype) {
 // first time a (dtype, kernel, dims, column blocks, log2 N) key is met; the
 // winner is cached for the process.
 struct TuneKey {
-    int dtype, kernel, dp, nsb, nlog;
+    int dtype, kernel, dp, nsb, nlog, cached;
     bool operator<(const TuneKey& o) const {
-        return std::tie(dtype, kernel, dp, nsb, nlog) < std::tie(o.dtype, o.kernel, o.dp, o.nsb, o.nlog);
+        return std::tie(dtype, kernel, dp, nsb, nlog, cached) <
+               std::tie(o.dtype, o.kernel, o.dp, o.nsb, o.nlog, o.cached);
     }
 };
 std::map<TuneKey, int> g_tuned_rt;   // guarded by the device scratch lock
@@ -173,6 +174,7 @@ struct Run {
     int bounds_mode = 0;
     int nsplit = 1, nrb = 0, rt = 2, nsplit_alloc = 1, nrb_alloc = 1;
     bool keep_solves = false;
+    bool cached = false;   // products stream a resident kernel matrix (kt)
     // device memory: points in FP64, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
     // consumes an FP32 copy q32 of the current Lanczos vector)
@@ -191,6 +193,8 @@ struct Run {
     double* pscale = nullptr;  // [nprob][CIQ_MAX_D] FP32-product difference scales
     double* t = nullptr;
     double* w = nullptr;
+    const double* kt = nullptr;  // resident kernel matrix (single FP64 problem) or nullptr
+    long long njs = 0;
     Dev d{};
     long long ysplit = 0;
     // host mirrors
@@ -262,6 +266,8 @@ struct Run {
         nrb = 0;
         for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rpb - 1) / rpb;
         nsplit = mvm_pick_nsplit(dtype, nrb, max_n, s);
+        if (cached && (max_n + 63) / 64 >= 8 && nrb * 8 >= 512)
+            nsplit = 8;   // one column range per XCD (split = block index mod 8)
         ysplit = (long long)rows_total * s;
     }
 
@@ -337,6 +343,8 @@ struct Run {
         a.ps2 = ps2;
         a.prob_done = (nprob > 1) ? d.prob_done : nullptr;
         a.done = &d.st->done;
+        a.kt = kt;
+        a.njs = njs;
         return a;
     }
 
@@ -417,7 +425,7 @@ int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
     }
     int nlog = 0;
     while ((1 << (nlog + 1)) <= r.rows_total) ++nlog;
-    const TuneKey key{r.dtype, r.kernel, r.dp, nsb, nlog};
+    const TuneKey key{r.dtype, r.kernel, r.dp, nsb, nlog, r.cached ? 1 : 0};
     auto it = g_tuned_rt.find(key);
     if (it == g_tuned_rt.end()) {
         hipEvent_t e0, e1;
@@ -501,6 +509,38 @@ void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob, int dty
     r.kernel = probs[0].kernel;
 }
 
+// Resident kernel matrix of one call: allocated after the decision in solve(),
+// freed when the call returns (after the device has drained its work).
+struct KCache {
+    double* ptr = nullptr;
+    ~KCache() {
+        if (ptr) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(ptr);
+        }
+    }
+};
+
+// Whether (and then where) a solve keeps K resident; CIQ_OK with *out = nullptr
+// means the products evaluate entries on the fly.
+int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* probs, KCache& kc) {
+    if (dtype != CIQ_F64 || nprob != 1 || o->kernel_cache == CIQ_CACHE_OFF) return CIQ_OK;
+    const size_t bytes = kcache_bytes(probs[0].n);
+    if (o->kernel_cache != CIQ_CACHE_ON) {
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        size_t limit = fr / 2;
+        if (o->cache_budget_mib > 0) limit = std::min(limit, (size_t)o->cache_budget_mib << 20);
+        if (bytes > limit) return CIQ_OK;
+    }
+    if (hipMalloc(&kc.ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        kc.ptr = nullptr;
+        return o->kernel_cache == CIQ_CACHE_ON ? CIQ_ENOMEM : CIQ_OK;
+    }
+    return CIQ_OK;
+}
+
 struct ScratchLock {
     std::unique_lock<std::mutex> lk;
     explicit ScratchLock(int dev) : lk(g_scratch[dev].mu) {}
@@ -521,9 +561,13 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
                              std::isfinite(o->lambda_max);
     const bool profile = o->profile != 0;
 
+    KCache kc;
+    STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
+
     // ---- sizing: bounds run (s = 1, Q = 0) and main run share the points ----
     Run<T> main;
     fill_problem_tables(main, probs, nprob, dtype);
+    main.cached = (kc.ptr != nullptr);
     main.dtype = dtype;
     main.s = s;
     main.Q = o->q;
@@ -540,6 +584,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     bnd.max_iter = steps;
     bnd.tol = 0.0;
     bnd.bounds_mode = 1;
+    bnd.cached = main.cached;
     bnd.plan(2);
 
     Sizer sz;
@@ -564,6 +609,21 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
 
     STCHK(main.upload_tables(st));
     STCHK(setup_points(main, probs, dtype, st));
+    if (kc.ptr) {
+        KBuildArgs ka{};
+        ka.xh = main.xh;
+        for (int k = 0; k < CIQ_MAX_D; ++k) ka.scale[k] = main.h_scale[k];
+        ka.n = main.h_n[0];
+        ka.dp = main.dp;
+        ka.kernel = main.kernel;
+        ka.ard = main.ard;
+        ka.nchunk = (int)(kcache_cols(ka.n) / 64);
+        ka.njs = (long long)(kcache_cols(ka.n) / 4);
+        ka.kt = kc.ptr;
+        HIPCHK(launch_kbuild(ka, st));
+        main.kt = bnd.kt = kc.ptr;
+        main.njs = bnd.njs = ka.njs;
+    }
 
     std::vector<double> lmin(nprob), lmax(nprob);
     int mvm_count = 0;
@@ -703,6 +763,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         }
         in.mvm_ms = mvm_ms;
         in.mvm_timed = mvm_timed;
+        in.kernel_cached = (kc.ptr != nullptr) ? 1 : 0;
     }
     return CIQ_OK;
 }

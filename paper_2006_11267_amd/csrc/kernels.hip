@@ -60,7 +60,10 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
         g.y = static_cast<double*>(a.y) + c0;
         const int nsb = (g.s + 15) / 16;
         hipError_t e;
-        if (dtype == CIQ_F64) {
+        if (dtype == CIQ_F64 && a.kt != nullptr) {
+            g.v = static_cast<const double*>(a.v) + c0;
+            e = launch_mvm_kt(g, nsb, st);
+        } else if (dtype == CIQ_F64) {
             g.v = static_cast<const double*>(a.v) + c0;
             if (a.kernel == CIQ_KERNEL_RBF)
                 e = a.ard ? launch_mvm_f64_rbf_ard(g, nsb, a.nrb, st) : launch_mvm_f64_rbf_iso(g, nsb, a.nrb, st);

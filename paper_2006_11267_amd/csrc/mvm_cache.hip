@@ -1,0 +1,274 @@
+// Resident kernel matrix for the FP64 path.
+//
+// msMINRES applies the same K in every iteration (Sec. 3.2). Evaluating the
+// entries costs ~49 FP64 VALU instructions per 64 entries on gfx950, and the
+// FP64 VALU shares its datapath with the FP64 MFMA (no overlap), so an
+// on-the-fly product pays entry generation plus contraction in every
+// iteration. When the matrix fits in device memory (N = 50,000 in FP64 is
+// 20 GB of the 288 GB), one build pass writes the unit-scale entries k(x_i, x_j)
+// once per call and every product streams them from HBM; the loads overlap
+// with the MFMA contraction, which is then the only bound.
+//
+// Layout ("operand-tiled"): with ib = i / 16, js = j / 4 (the 4-column step)
+// and lane = (i % 16) + 16 * (j % 4), the entry K[i][j] sits at
+//     kt[((ib * (njs / 2) + js / 2) * 64 + lane) * 2 + js % 2],
+// njs = padded columns / 4. One 64-lane load of 16 bytes per lane returns,
+// in lane l, the A-operands of v_mfma_f64_16x16x4_f64 for two consecutive
+// steps, K[16 ib + l % 16][4 js + l / 16] for js = 2p, 2p + 1, from 1 KB of
+// contiguous memory (16-byte lanes stream measurably faster than 8-byte
+// ones). Rows are padded to a multiple of 128 and columns to a multiple of 64;
+// the padding holds finite entries of zero points, which meet zero rows of V.
+#include "mvm_mfma.h"
+
+namespace ciq {
+namespace {
+
+using mfma::doublex4;
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+
+// ---- build pass ------------------------------------------------------------
+// grid.x: 64-row blocks (one 16-row tile per wave), grid.y: column ranges.
+template <int KERNEL, int DP, bool ARD>
+__global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
+    constexpr int BN = 64;
+    constexpr int XE = BN * DP;
+    __shared__ double xs[XE];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = blockIdx.x * 4 + wave;
+    const int n = a.n;
+    const int i = tile * 16 + (lane & 15);
+    double sc[DP];
+#pragma unroll
+    for (int k = 0; k < DP; ++k) sc[k] = a.scale[k];
+    const double sc0sq = sc[0] * sc[0];
+    double xi[DP];
+#pragma unroll
+    for (int k = 0; k < DP; ++k) xi[k] = (i < n) ? a.xh[(long long)i * DP + k] : 0.0;
+
+    const int nchunk = a.nchunk;
+    const int c0 = (int)(((long long)blockIdx.y * nchunk) / gridDim.y);
+    const int c1 = (int)(((long long)(blockIdx.y + 1) * nchunk) / gridDim.y);
+    doublex2* __restrict__ out = reinterpret_cast<doublex2*>(a.kt + (size_t)tile * a.njs * 64) + lane;
+    auto entry = [&](int jl) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+            const double dd = xi[k] - xs[jl * DP + k];
+            if constexpr (ARD) {
+                const double u = dd * sc[k];
+                r2 = fma(u, u, r2);
+            } else {
+                r2 = fma(dd, dd, r2);
+            }
+        }
+        if constexpr (!ARD) r2 *= sc0sq;
+        return mfma::kentry64<KERNEL>(r2);
+    };
+    for (int c = c0; c < c1; ++c) {
+        __syncthreads();
+        for (int e = tid; e < XE; e += 256) {
+            const int j = c * BN + e / DP;
+            xs[e] = (j < n) ? a.xh[(long long)c * BN * DP + e] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int p = 0; p < 8; ++p) {
+            doublex2 kv;
+            kv[0] = entry(8 * p + (lane >> 4));
+            kv[1] = entry(8 * p + 4 + (lane >> 4));
+            __builtin_nontemporal_store(kv, out + (size_t)(c * 8 + p) * 64);
+        }
+    }
+}
+
+template <int KERNEL, bool ARD>
+hipError_t launch_kbuild_dp(const KBuildArgs& a, dim3 grid, hipStream_t st) {
+    switch (a.dp) {
+        case 4: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 4, ARD>), grid, dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 6, ARD>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 8, ARD>), grid, dim3(256), 0, st, a); break;
+        case 10: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 10, ARD>), grid, dim3(256), 0, st, a); break;
+        case 12: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 12, ARD>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 16, ARD>), grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+// ---- streaming product -----------------------------------------------------
+// Y_split = o2 * K[rows, cols(split)] V[cols(split)] (+ s2 V on split 0).
+// 1-D grid of nrb * nsplit blocks, split = blockIdx.x % nsplit: consecutive
+// blocks go to different XCDs, so with nsplit a multiple of 8 every XCD works
+// on one column range and keeps that slice of V in its own L2.
+// A block of 4 waves owns 64 * RT rows; wave w owns 16-row tiles
+// 4 * RT * rb + RT * w + rt. Per 64-column chunk the rows of V are staged in
+// LDS (as in the on-the-fly product) and the wave's 16 * RT operand loads of
+// the next chunk are in flight while the current chunk is contracted.
+template <int NSB, int RT, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
+    constexpr int NT = 64 * WAVES;
+    constexpr int BN = 64;
+    constexpr int S16 = NSB * 16;
+    constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
+    constexpr int VPT = BN * S16 / NT;
+    constexpr int VROWS = NT / S16;
+    __shared__ double vs[BN * VST];
+
+    if (mfma::done_now(a.done)) return;
+    const int nsplit = a.nsplit;
+    const int split = (int)(blockIdx.x % (unsigned)nsplit);
+    const int rb = (int)(blockIdx.x / (unsigned)nsplit);
+    const int n = a.n;
+    const double o2 = a.o2, s2 = a.s2;
+    const double* __restrict__ v = static_cast<const double*>(a.v);
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: keeps bases in SGPRs
+    const int tile0 = (rb * WAVES + wave) * RT;
+    const int row0 = tile0 * 16;
+
+    const int nchunk = (n + BN - 1) / BN;
+    const int c0 = (int)(((long long)split * nchunk) / nsplit);
+    const int c1 = (int)(((long long)(split + 1) * nchunk) / nsplit);
+
+    doublex4 acc[RT][NSB];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) acc[rt][sb] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+    // V staging: thread (vr, vc) moves rows vr + k * VROWS, column vc of the
+    // chunk. Chunks wholly inside the matrix with every column live take the
+    // unchecked path: a uniform base per row group plus one fixed per-lane
+    // offset, so the loads cost no vector ALU work.
+    const int vr = tid / S16, vc = tid - (tid / S16) * S16;
+    const unsigned voff = (unsigned)(vr * ldv + vc);
+    const bool full_cols = (s == S16);
+    double vreg[VPT];
+    auto fetch_v = [&](int c) {
+        const int j0 = c * BN;
+        if (full_cols && j0 + BN <= n) {
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) vreg[k] = (v + (size_t)(j0 + k * VROWS) * ldv)[voff];
+        } else {
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+                const int j = j0 + vr + k * VROWS;
+                vreg[k] = (vc < s && j < n) ? v[(size_t)j * ldv + vc] : 0.0;
+            }
+        }
+    };
+    // operand loads: uniform base per (16-row tile, chunk), lane offset l + 64 st
+    const double* kb[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) kb[rt] = a.kt + (size_t)(tile0 + rt) * a.njs * 64;
+    double kc[RT][16], kn[RT][16];
+    auto fetch_k = [&](int c, double (&dst)[RT][16]) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const doublex2* base = reinterpret_cast<const doublex2*>(kb[rt] + (size_t)c * 1024);
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                const doublex2 x = __builtin_nontemporal_load(base + (unsigned)(lane + 64 * p));
+                dst[rt][2 * p] = x[0];
+                dst[rt][2 * p + 1] = x[1];
+            }
+        }
+    };
+    // one chunk: publish its V rows, start the next chunk's loads, contract;
+    // the B operands of step st + 1 are read from LDS before step st's MFMAs
+    auto chunk = [&](int c, double (&cur)[RT][16], double (&nxt)[RT][16]) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
+        __syncthreads();
+        if (c + 1 < c1) {
+            fetch_v(c + 1);
+            fetch_k(c + 1, nxt);
+        }
+        double bcur[NSB], bnxt[NSB];
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) bcur[sb] = vs[(lane >> 4) * VST + sb * 16 + (lane & 15)];
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            if (st + 1 < 16) {
+                const int jn = 4 * (st + 1) + (lane >> 4);
+#pragma unroll
+                for (int sb = 0; sb < NSB; ++sb) bnxt[sb] = vs[jn * VST + sb * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt][sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[rt][st], bcur[sb], acc[rt][sb], 0, 0, 0);
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb) bcur[sb] = bnxt[sb];
+        }
+    };
+    if (c0 < c1) {
+        fetch_v(c0);
+        fetch_k(c0, kc);
+    }
+    // two chunks per trip so the operand buffers swap roles without copies
+    for (int c = c0; c < c1; c += 2) {
+        chunk(c, kc, kn);
+        if (c + 1 < c1) chunk(c + 1, kn, kc);
+    }
+
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) {
+            const int cc = sb * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + rt * 16 + (lane >> 4) + 4 * r;
+                if (i < n && cc < s) {
+                    double val = o2 * acc[rt][sb][r];
+                    if (split == 0) val = fma(s2, v[(long long)i * ldv + cc], val);
+                    y[(long long)i * ldy + cc] = val;
+                }
+            }
+        }
+    }
+}
+
+template <int NSB>
+hipError_t launch_kt_nsb(const MvmArgs& a, int grid, hipStream_t st) {
+    if (a.rt == 1)
+        hipLaunchKernelGGL((mvm_kt_kernel<NSB, 1, 4>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((mvm_kt_kernel<NSB, 2, 4>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t kcache_rows(int n) { return ((size_t)n + 127) / 128 * 128; }
+size_t kcache_cols(int n) { return ((size_t)n + 63) / 64 * 64; }
+size_t kcache_bytes(int n) { return kcache_rows(n) * kcache_cols(n) * sizeof(double); }
+
+hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st) {
+    const int nrb64 = (int)(kcache_rows(a.n) / 64);
+    // enough blocks to fill 256 CUs several times over
+    int ny = 1;
+    while ((long long)nrb64 * ny < 4096 && ny < a.nchunk) ny *= 2;
+    dim3 grid(nrb64, ny);
+    if (a.kernel == CIQ_KERNEL_RBF)
+        return a.ard ? launch_kbuild_dp<CIQ_KERNEL_RBF, true>(a, grid, st)
+                     : launch_kbuild_dp<CIQ_KERNEL_RBF, false>(a, grid, st);
+    return a.ard ? launch_kbuild_dp<CIQ_KERNEL_MATERN52, true>(a, grid, st)
+                 : launch_kbuild_dp<CIQ_KERNEL_MATERN52, false>(a, grid, st);
+}
+
+hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
+    const int grid = a.nrb * a.nsplit;
+    switch (nsb) {
+        case 1: return launch_kt_nsb<1>(a, grid, st);
+        case 2: return launch_kt_nsb<2>(a, grid, st);
+        default: return launch_kt_nsb<4>(a, grid, st);
+    }
+}
+
+}  // namespace ciq

@@ -53,7 +53,8 @@ class Problem:
         return p, arr  # keep arr alive with p
 
 
-def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, check_every=0, profile=False):
+def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, check_every=0, profile=False,
+          kernel_cache="auto", cache_budget_mib=0):
     o = L.ciq_opts()
     o.dtype = dtype_code
     o.q = int(q)
@@ -65,6 +66,8 @@ def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, ch
         o.lambda_min, o.lambda_max = float(bounds[0]), float(bounds[1])
     o.check_every = int(check_every)
     o.profile = 1 if profile else 0
+    o.kernel_cache = L.CACHE_MODES[kernel_cache]
+    o.cache_budget_mib = int(cache_budget_mib)
     return o
 
 
@@ -109,7 +112,7 @@ def ciq_eig_bounds(problem: Problem, steps: int = 20, v0: Optional[torch.Tensor]
 
 
 def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves, lanczos_steps, seed,
-           check_every, profile):
+           check_every, profile, kernel_cache, cache_budget_mib):
     lib = L.load()
     code = _dtype_code(problem.x, precision)
     b2 = b if b.dim() == 2 else b.reshape(-1, 1)
@@ -119,7 +122,8 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
     out = torch.empty((n, s), dtype=_elem_dtype(code), device=b.device)
     solves = torch.empty((n, q, s), dtype=_elem_dtype(code), device=b.device) if keep_solves else None
     p, keep = problem.c_struct()
-    o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile)
+    o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, kernel_cache,
+              cache_budget_mib)
     info = L.ciq_info()
     fn = getattr(lib, fn_name)
     L.check(fn(ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s, b2.stride(0),
@@ -132,18 +136,20 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
 
 def ciq_invsqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                     precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
-                    lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False):
+                    lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
+                    kernel_cache: str = "auto", cache_budget_mib: int = 0):
     """K^{-1/2} B -> (out, info, solves or None)."""
     return _solve("ciq_invsqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib)
 
 
 def ciq_sqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                  precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
-                 lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False):
+                 lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
+                 kernel_cache: str = "auto", cache_budget_mib: int = 0):
     """K^{1/2} B -> (out, info, solves or None)."""
     return _solve("ciq_sqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib)
 
 
 def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tensor], q: int = 12,

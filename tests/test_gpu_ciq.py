@@ -18,17 +18,34 @@ def _dense(p):
     return okern.kernel_matrix(p.kernel, p.x.astype(np.float64), p.lengthscale, p.outputscale, p.noise)
 
 
+def _oracle_spread(K, b, bounds, q, J, tol, mode, ref, seeds=2):
+    """How far the oracle's own result moves when every entry of K is
+    perturbed by one ulp (2.2e-16 relative, independent per entry): the scale
+    of the rounding differences between two correct FP64 kernel products
+    (entry evaluation and summation order) at this (K, J)."""
+    spread = 0.0
+    for seed in range(seeds):
+        rng = np.random.default_rng(100 + seed)
+        E = rng.standard_normal(K.shape)
+        Kp = K * (1.0 + 2.2e-16 * (E + E.T) / np.sqrt(2.0))
+        alt, _ = ociq.ciq(lambda v: Kp @ v, b, bounds[0], bounds[1], q, J, tol, mode)
+        spread = max(spread, colwise_rel(alt, ref).max())
+    return spread
+
+
 def _gpu_problem(ciq, torch, p):
     return ciq.Problem(torch.from_numpy(np.ascontiguousarray(p.x)).cuda(), p.kernel, p.lengthscale,
                        p.outputscale, p.noise)
 
 
+@pytest.mark.parametrize("cache", ["on", "off"])
 @pytest.mark.parametrize("J", [1, 2, 5, 10])
 @pytest.mark.parametrize("mode", ["invsqrt", "sqrt"])
-def test_fp64_recurrence_parity_small_j(mode, J):
+def test_fp64_recurrence_parity_small_j(mode, J, cache):
     """Before Lanczos loses orthogonality the finite-precision iterates are
     stable, so GPU and oracle must agree to rounding: RBF N=1024 d=3 (first
-    workload's inputs), Q=8, fixed J, no early stop."""
+    workload's inputs), Q=8, fixed J, no early stop; with the resident kernel
+    matrix and with entries evaluated in every product."""
     torch = torch_cuda()
     ciq = ciq_module()
     import workloads
@@ -37,10 +54,11 @@ def test_fp64_recurrence_parity_small_j(mode, J):
     K = _dense(p)
     lam = np.linalg.eigvalsh(K)
     bounds = (lam[0], lam[-1])
-    announce(f"ciq f64 small-J parity {mode} J={J}")
+    announce(f"ciq f64 small-J parity {mode} J={J} cache={cache}")
     fn = ciq.ciq_invsqrt_mvm if mode == "invsqrt" else ciq.ciq_sqrt_mvm
     out, info, solves = fn(_gpu_problem(ciq, torch, p), torch.from_numpy(p.b).cuda(), q=8, max_iter=J,
-                           tol=0.0, bounds=bounds, keep_solves=True)
+                           tol=0.0, bounds=bounds, keep_solves=True, kernel_cache=cache)
+    assert info["kernel_cached"] == (cache == "on")
     ref, oinfo, t, w, X = ociq.ciq(lambda v: K @ v, p.b, bounds[0], bounds[1], 8, J, 0.0, mode,
                                    return_solves=True)
     assert info["iters"] == oinfo.iters == J
@@ -87,9 +105,10 @@ def test_fp64_workload1(mode):
     assert colwise_rel(out, exact).max() < 1.2 * own
 
 
+@pytest.mark.parametrize("cache", ["on", "off"])
 @pytest.mark.parametrize("n,s,kind,q", [(777, 5, "matern52", 6), (64, 3, "rbf", 15), (1, 2, "rbf", 4),
                                         (200, 17, "rbf", 8)])
-def test_fp64_ragged_shapes(n, s, kind, q):
+def test_fp64_ragged_shapes(n, s, kind, q, cache):
     torch = torch_cuda()
     ciq = ciq_module()
     rng = np.random.default_rng(n + s)
@@ -101,11 +120,12 @@ def test_fp64_ragged_shapes(n, s, kind, q):
     K = okern.kernel_matrix(kind, x, [0.3], 1.2, 0.02)
     lam = np.linalg.eigvalsh(K)
     bounds = (lam[0], lam[-1])
-    announce(f"ciq f64 ragged n={n} s={s} {kind} q={q}")
+    announce(f"ciq f64 ragged n={n} s={s} {kind} q={q} cache={cache}")
     prob = ciq.Problem(torch.from_numpy(x).cuda(), kind, [0.3], 1.2, 0.02)
     for mode, fn in [("invsqrt", ciq.ciq_invsqrt_mvm), ("sqrt", ciq.ciq_sqrt_mvm)]:
         out, info, solves = fn(prob, torch.from_numpy(b).cuda(), q=q, max_iter=1500, tol=1e-11,
-                               bounds=bounds, keep_solves=True)
+                               bounds=bounds, keep_solves=True, kernel_cache=cache)
+        assert info["kernel_cached"] == (cache == "on")
         ref, oinfo, t, w, X = ociq.ciq(lambda v: K @ v, b, bounds[0], bounds[1], q, 1500, 1e-11, mode,
                                        return_solves=True)
         out = out.cpu().numpy()
@@ -119,6 +139,59 @@ def test_fp64_ragged_shapes(n, s, kind, q):
         for qi in range(q):
             assert colwise_rel(sv[:, qi, nz], X[qi][:, nz]).max() < 1e-8
         assert info["converged"]
+
+
+@pytest.mark.parametrize("kind,n,s,d,ard", [("matern52", 3001, 20, 5, True), ("rbf", 5000, 64, 8, False),
+                                            ("matern52", 4500, 64, 6, False), ("rbf", 700, 1, 12, True)])
+def test_resident_matrix_small_j_parity(kind, n, s, d, ard):
+    """The streamed resident matrix against the oracle at fixed small J over
+    tile-spanning ragged sizes, including the one-range-per-XCD split
+    (n >= 4096 rows, 64 columns) and single-column products. The bar is 10x
+    the oracle's own rounding spread (entries of K perturbed by one ulp), at
+    least 1e-12."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(n + 7 * d)
+    x = rng.random((n, d))
+    b = rng.standard_normal((n, s))
+    ls = list(np.linspace(0.25, 0.9, d)) if ard else [0.4]
+    K = okern.kernel_matrix(kind, x, ls, 1.3, 0.05)
+    lam = np.linalg.eigvalsh(K)
+    bounds = (lam[0], lam[-1])
+    announce(f"ciq f64 resident K small-J {kind} n={n} s={s} d={d} ard={ard}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), kind, ls, 1.3, 0.05)
+    for mode, fn in [("invsqrt", ciq.ciq_invsqrt_mvm), ("sqrt", ciq.ciq_sqrt_mvm)]:
+        out, info, _ = fn(prob, torch.from_numpy(b).cuda(), q=6, max_iter=6, tol=0.0, bounds=bounds,
+                          kernel_cache="on")
+        assert info["kernel_cached"]
+        ref, oinfo = ociq.ciq(lambda v: K @ v, b, bounds[0], bounds[1], 6, 6, 0.0, mode)
+        assert info["iters"] == oinfo.iters == 6
+        bar = max(10.0 * _oracle_spread(K, b, bounds, 6, 6, 0.0, mode, ref), 1e-12)
+        gap = colwise_rel(out.cpu().numpy(), ref).max()
+        assert gap < bar, (mode, gap, bar)
+
+
+def test_kernel_cache_policy():
+    """auto keeps K only within the budget; the FP32 path never caches."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(5)
+    n = 1024                                   # resident matrix: 1024 x 1024 doubles = 8 MiB
+    x = rng.random((n, 3))
+    b = rng.standard_normal((n, 2))
+    announce("kernel cache policy")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), "rbf", [0.3], 1.0, 0.1)
+    bt = torch.from_numpy(b).cuda()
+    _, i_auto, _ = ciq.ciq_invsqrt_mvm(prob, bt, q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0))
+    _, i_small, _ = ciq.ciq_invsqrt_mvm(prob, bt, q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
+                                        cache_budget_mib=4)
+    _, i_big, _ = ciq.ciq_invsqrt_mvm(prob, bt, q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
+                                      cache_budget_mib=16)
+    assert i_auto["kernel_cached"] and not i_small["kernel_cached"] and i_big["kernel_cached"]
+    p32 = ciq.Problem(torch.from_numpy(x.astype(np.float32)).cuda(), "rbf", [0.3], 1.0, 0.1)
+    _, i32, _ = ciq.ciq_invsqrt_mvm(p32, bt.float(), q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
+                                    kernel_cache="on")
+    assert not i32["kernel_cached"]
 
 
 @pytest.mark.parametrize("kind,n,s,d", [("matern52", 2000, 16, 6), ("rbf", 1500, 33, 8), ("rbf", 999, 64, 3)])
