@@ -30,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix peaks
+# HBM bytes per launch of the streamed resident-K product at this workload
+# (N = 50,000, S = 64): FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
+# runs of `bench.py --counters`, each scaled by the same counter's reading for
+# a plain 512 MiB device copy (profiles/mvm_kt_kernel_matern52_n50000_s64_hbm_traffic.md).
+KT_TRAFFIC_BYTES = 2.0711e10
 METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
 
 
@@ -192,7 +197,8 @@ def main() -> int:
         },
         "roofline": {
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak,
+            "traffic": (KT_TRAFFIC_BYTES if info["kernel_cached"] and (n, s) == (50000, 64) else None),
             "kernel": ("mvm_kt_kernel" if info["kernel_cached"] else
                        "mvm_f64mfma_kernel" if args.precision == "f64" else "mvm_f32_kernel"),
             "avg_ms": avg_ms, "launches": mvm_n,

@@ -103,7 +103,7 @@ hipError_t launch_kbuild_dp(const KBuildArgs& a, dim3 grid, hipStream_t st) {
 // 4 * RT * rb + RT * w + rt. Per 64-column chunk the rows of V are staged in
 // LDS (as in the on-the-fly product) and the wave's 16 * RT operand loads of
 // the next chunk are in flight while the current chunk is contracted.
-template <int NSB, int RT, int WAVES>
+template <int NSB, int RT, int WAVES, int KD>
 __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
     constexpr int NT = 64 * WAVES;
     constexpr int BN = 64;
@@ -163,7 +163,9 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
     const double* kb[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) kb[rt] = a.kt + (size_t)(tile0 + rt) * a.njs * 64;
-    double kc[RT][16], kn[RT][16];
+    // KD chunks of operands in flight: chunk c + KD - 1 is requested while c
+    // is contracted
+    double kq[KD][RT][16];
     auto fetch_k = [&](int c, double (&dst)[RT][16]) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
@@ -176,17 +178,15 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
             }
         }
     };
-    // one chunk: publish its V rows, start the next chunk's loads, contract;
-    // the B operands of step st + 1 are read from LDS before step st's MFMAs
-    auto chunk = [&](int c, double (&cur)[RT][16], double (&nxt)[RT][16]) {
+    // one chunk: publish its V rows, start later loads, contract; the B
+    // operands of step st + 1 are read from LDS before step st's MFMAs
+    auto chunk = [&](int c, double (&cur)[RT][16], double (&far)[RT][16]) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
         __syncthreads();
-        if (c + 1 < c1) {
-            fetch_v(c + 1);
-            fetch_k(c + 1, nxt);
-        }
+        if (c + 1 < c1) fetch_v(c + 1);
+        if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
         double bcur[NSB], bnxt[NSB];
 #pragma unroll
         for (int sb = 0; sb < NSB; ++sb) bcur[sb] = vs[(lane >> 4) * VST + sb * 16 + (lane & 15)];
@@ -206,14 +206,15 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
             for (int sb = 0; sb < NSB; ++sb) bcur[sb] = bnxt[sb];
         }
     };
-    if (c0 < c1) {
-        fetch_v(c0);
-        fetch_k(c0, kc);
-    }
-    // two chunks per trip so the operand buffers swap roles without copies
-    for (int c = c0; c < c1; c += 2) {
-        chunk(c, kc, kn);
-        if (c + 1 < c1) chunk(c + 1, kn, kc);
+    if (c0 < c1) fetch_v(c0);
+#pragma unroll
+    for (int q = 0; q + 1 < KD; ++q)
+        if (c0 + q < c1) fetch_k(c0 + q, kq[q]);
+    // KD chunks per trip so the operand buffers rotate without copies
+    for (int c = c0; c < c1; c += KD) {
+#pragma unroll
+        for (int q = 0; q < KD; ++q)
+            if (c + q < c1) chunk(c + q, kq[q], kq[(q + KD - 1) % KD]);
     }
 
 #pragma unroll
@@ -237,9 +238,9 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
 template <int NSB>
 hipError_t launch_kt_nsb(const MvmArgs& a, int grid, hipStream_t st) {
     if (a.rt == 1)
-        hipLaunchKernelGGL((mvm_kt_kernel<NSB, 1, 4>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((mvm_kt_kernel<NSB, 1, 4, 2>), dim3(grid), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((mvm_kt_kernel<NSB, 2, 4>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((mvm_kt_kernel<NSB, 2, 4, 2>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1,15 +1,21 @@
 """Full-size (N = 50,000, Matern-5/2, d = 6, kappa ~ 2.5e6) accuracy at the
 benchmark's settings. The oracle cannot run msMINRES at this size, so the
 checks are (i) a property that holds at any size, K^{-1/2} (K^{1/2} b) = b,
-and (ii) the result at tol 1e-4 against the library's FP64 path run to tol
-1e-9 (the FP64 path is held to the oracle at smaller sizes, and its kernel
-product to the oracle's rows at this size)."""
+and (ii) the result against the library's FP64 path run to tol 1e-9 (the FP64
+path is held to the oracle at smaller sizes, and its kernel product to the
+oracle's rows at this size).
+
+At this conditioning a MINRES stopping tolerance of 1e-4 leaves ~1.5e-4
+(K^{-1/2}B) and ~4e-4 (K^{1/2}B) relative error; the benchmark stops at 5e-6,
+which these tests hold to 1e-4."""
 import numpy as np
 import pytest
 
 from gpu_util import announce, ciq_module, colwise_rel, torch_cuda
 
 pytestmark = pytest.mark.gpu
+
+BENCH_TOL = 5e-6     # the benchmark's stopping tolerance
 
 
 def _problem(ciq, torch, dtype, s):
@@ -26,8 +32,8 @@ def test_round_trip_full_size_fp64():
     ciq = ciq_module()
     wl, prob, b = _problem(ciq, torch, np.float64, 4)
     announce("full-size round trip f64 n=50000 s=4")
-    half, i1, _ = ciq.ciq_sqrt_mvm(prob, b, q=15, max_iter=4000, tol=1e-5, seed=4001)
-    back, i2, _ = ciq.ciq_invsqrt_mvm(prob, half, q=15, max_iter=4000, tol=1e-5, seed=4001)
+    half, i1, _ = ciq.ciq_sqrt_mvm(prob, b, q=15, max_iter=6000, tol=BENCH_TOL, seed=4001)
+    back, i2, _ = ciq.ciq_invsqrt_mvm(prob, half, q=15, max_iter=6000, tol=BENCH_TOL, seed=4001)
     err = colwise_rel(back.cpu().numpy(), b.cpu().numpy()).max()
     print(f"round trip rel err {err:.3e} iters {i1['iters']} {i2['iters']}", flush=True)
     assert i1["converged"] and i2["converged"]
@@ -52,14 +58,14 @@ def tight_fp64():
 
 @pytest.mark.parametrize("mode", ["invsqrt", "sqrt"])
 def test_fp64_at_bench_settings_full_size(tight_fp64, mode):
-    """The benchmark's path (FP64 product, tol 1e-4) meets 1e-4 relative error."""
+    """The benchmark's path (FP64 product, tol 5e-6) meets 1e-4 relative error."""
     torch = torch_cuda()
     ciq = ciq_module()
     bounds, inv, sq = tight_fp64
     wl, p64, b64 = _problem(ciq, torch, np.float64, 4)
-    announce(f"full-size f64 tol 1e-4 {mode} n=50000 s=4")
+    announce(f"full-size f64 tol {BENCH_TOL} {mode} n=50000 s=4")
     fn = ciq.ciq_invsqrt_mvm if mode == "invsqrt" else ciq.ciq_sqrt_mvm
-    out, info, _ = fn(p64, b64, q=15, max_iter=4000, tol=wl.tol, bounds=bounds)
+    out, info, _ = fn(p64, b64, q=15, max_iter=6000, tol=BENCH_TOL, bounds=bounds)
     err = colwise_rel(out.cpu().numpy(), inv if mode == "invsqrt" else sq).max()
     print(f"f64 {mode} rel err {err:.3e} iters {info['iters']}", flush=True)
     assert info["converged"]
