@@ -42,7 +42,7 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(p, iters: int, q: int, sample_rows: int = 4096) -> dict:
+def cpu_baseline(p, iters: int, q: int, sample_rows: int = 12288) -> dict:
     """The oracle, as written, on a bounded sample of the same workload:
     rows [0, sample_rows) of K B (its blocked kernel product) plus two
     full-size msMINRES vector steps (with a trivial operator), extrapolated to

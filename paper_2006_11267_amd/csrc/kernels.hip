@@ -194,26 +194,34 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, const T* y, long long 
 }
 
 // Column sums of the block partials, fixed order: colsum[k * ncol + g] =
-// sum_b dots[p][b][c][k]. Block: 64 columns x 4 lanes.
-__global__ __launch_bounds__(256) void colsum_kernel(Dev d, int k) {
-    __shared__ double sh[256];
+// sum_b dots[p][b][c][k]. Block: 64 columns x 16 lanes; lane r sums blocks
+// r, r + 16, ... (independent loads in flight), then the 16 lane sums are
+// added in lane order.
+__global__ __launch_bounds__(1024) void colsum_kernel(Dev d, int k) {
+    __shared__ double sh[1024];
     if (d.st->done) return;
-    const int cl = threadIdx.x & 63, lane4 = threadIdx.x >> 6;
+    const int cl = threadIdx.x & 63, lane = threadIdx.x >> 6;
     const int g = blockIdx.x * 64 + cl;
     double acc = 0.0;
     if (g < d.ncol) {
         const int p = g / d.s, c = g - p * d.s;
         const double* base = d.dots + ((long long)p * d.dots_blocks * d.s + c) * 2 + k;
-        for (int b = lane4; b < d.dots_blocks; b += 4) acc += base[(long long)b * d.s * 2];
+        const long long stride = (long long)d.s * 2;
+#pragma unroll 8
+        for (int b = lane; b < d.dots_blocks; b += 16) acc += base[(long long)b * stride];
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
-    if (lane4 == 0 && g < d.ncol)
-        d.colsum[(long long)k * d.ncol + g] = sh[cl] + sh[64 + cl] + sh[128 + cl] + sh[192 + cl];
+    if (lane == 0 && g < d.ncol) {
+        double t = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) t += sh[r * 64 + cl];
+        d.colsum[(long long)k * d.ncol + g] = t;
+    }
 }
 
 hipError_t launch_colsum(const Dev& d, int k, hipStream_t st) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((d.ncol + 63) / 64), dim3(256), 0, st, d, k);
+    hipLaunchKernelGGL(colsum_kernel, dim3((d.ncol + 63) / 64), dim3(1024), 0, st, d, k);
     return hipGetLastError();
 }
 
