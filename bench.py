@@ -29,7 +29,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix peaks
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}   # MI355X dense matrix peaks
 # HBM bytes per launch of the streamed resident-K product at this workload
 # (N = 50,000, S = 64): FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
 # runs of `bench.py --counters`, each scaled by the same counter's reading for
@@ -92,9 +92,9 @@ def main() -> int:
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
-    ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
-                    help="f64: FP64 MFMA product (meets 1e-4 at this conditioning); "
-                         "f32: FP32 MFMA product (~2e-4 at kappa 2.5e6)")
+    ap.add_argument("--precision", choices=["f64", "f32", "bf16x3", "f16x3"], default="f64",
+                    help="f64: FP64 MFMA product (meets 1e-4 at this conditioning); f32: FP32 MFMA product "
+                         "(~2e-4 at kappa 2.5e6); bf16x3 / f16x3: split-operand half-precision products")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -108,6 +108,7 @@ def main() -> int:
     p = wl.problems[0]
     dev = torch.device("cuda:0")
     tdt = torch.float64 if args.precision == "f64" else torch.float32
+    prec = None if args.precision in ("f64", "f32") else args.precision
     x = torch.from_numpy(p.x).to(dev).to(tdt)        # inputs resident in HBM before timing
     b = torch.from_numpy(p.b).to(dev).to(tdt)
     prob = ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise)
@@ -117,7 +118,7 @@ def main() -> int:
 
     def step(profile=False):
         return ciq.ciq_sqrt_mvm(prob, b, q=q, max_iter=args.max_iter, tol=tol, seed=4001, profile=profile,
-                                kernel_cache=args.kernel_cache)
+                                kernel_cache=args.kernel_cache, precision=prec)
 
     if args.counters:
         src = torch.empty(64 << 20, dtype=torch.float64, device=dev).normal_()
@@ -125,7 +126,7 @@ def main() -> int:
         dst.copy_(src)                       # reference copy: 512 MiB read + 512 MiB written
         torch.cuda.synchronize()
         out, info, _ = ciq.ciq_sqrt_mvm(prob, b, q=q, max_iter=4, tol=tol, seed=4001,
-                                        kernel_cache=args.kernel_cache)
+                                        kernel_cache=args.kernel_cache, precision=prec)
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "copy_bytes": src.numel() * 8, "iters": info["iters"],
                           "mvm_count": info["mvm_count"]}), flush=True)
@@ -154,24 +155,27 @@ def main() -> int:
 
     accuracy = None
     if args.check_cols > 0:
+        # reference: the FP64 path on the same (rounded) inputs, same bounds, tol 1e-10
         k = min(args.check_cols, s)
-        bk = b[:, :k].contiguous()
-        ref, rinfo, _ = ciq.ciq_sqrt_mvm(prob, bk, q=q, max_iter=20000, tol=1e-10, seed=4001,
-                                         bounds=(info["lambda_min"], info["lambda_max"]),
-                                         kernel_cache=args.kernel_cache)
+        bk = b[:, :k].double().contiguous()
+        p64 = ciq.Problem(x.double().contiguous(), p.kernel, p.lengthscale, p.outputscale, p.noise)
+        ref, rinfo, _ = ciq.ciq_sqrt_mvm(p64, bk, q=q, max_iter=20000, tol=1e-10, seed=4001,
+                                         bounds=(info["lambda_min"], info["lambda_max"]))
         torch.cuda.synchronize()
         o = out[:, :k].double().cpu().numpy()
         r = ref.double().cpu().numpy()
         rel = np.linalg.norm(o - r, axis=0) / np.linalg.norm(r, axis=0)
         accuracy = {"max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)), "columns": k,
-                    "reference": f"same path, same bounds, tol 1e-10 ({rinfo['iters']} iterations)"}
+                    "reference": f"FP64 path, same inputs and bounds, tol 1e-10 ({rinfo['iters']} iterations)"}
         log(f"accuracy on {k} columns: max {rel.max():.2e} median {np.median(rel):.2e}")
 
     # dominant kernel: the kernel product, timed live with HIP events inside the solves
     mvm_ms = sum(i["mvm_ms"] for i in infos)
     mvm_n = sum(i["mvm_timed"] for i in infos)
     avg_ms = mvm_ms / max(mvm_n, 1)
-    flops = 2.0 * n * n * s                 # algorithmic tile x V contraction per launch
+    # algorithmic tile x V contraction per launch; the split forms run it as
+    # three half-precision MFMA products
+    flops = 2.0 * n * n * s * (3 if args.precision in ("bf16x3", "f16x3") else 1)
     achieved = flops / (avg_ms * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[args.precision]
 
@@ -200,7 +204,7 @@ def main() -> int:
             "frac": achieved / peak,
             "traffic": (KT_TRAFFIC_BYTES if info["kernel_cached"] and (n, s) == (50000, 64) else None),
             "kernel": ("mvm_kt_kernel" if info["kernel_cached"] else
-                       "mvm_f64mfma_kernel" if args.precision == "f64" else "mvm_f32_kernel"),
+                       {"f64": "mvm_f64mfma_kernel", "f32": "mvm_f32_kernel"}.get(args.precision, "mvm_x3_kernel")),
             "avg_ms": avg_ms, "launches": mvm_n,
         },
     }

@@ -55,10 +55,15 @@ extern "C" {
 #define CIQ_KERNEL_MATERN52  1   /* k = (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r)        */
 /* r^2 = sum_d (x_d - x'_d)^2 / l_d^2; l isotropic (1 value) or ARD (d values)      */
 
-#define CIQ_F64     0   /* double everywhere                                        */
-#define CIQ_F32     1   /* float vectors, float kernel tiles, FP32 MFMA contraction  */
-#define CIQ_BF16X3  2   /* float vectors; tile*V on bf16 MFMA with hi/lo split       */
-#define CIQ_F16X3   3   /* float vectors; tile*V on fp16 MFMA with hi/lo split       */
+#define CIQ_F64     0   /* double everywhere; FP64 entries, FP64 MFMA contraction    */
+#define CIQ_F32     1   /* float inputs/outputs; FP32 entries, FP32 MFMA contraction
+                           (FP64 running sums); FP64 Krylov vectors and scalars    */
+#define CIQ_BF16X3  2   /* as CIQ_F32, but the entries and V are split into BF16
+                           hi + scaled lo parts: K V ~ Kh Vh + 2^-8 (Kh Vl + Kl Vh)
+                           on bf16 MFMA, FP32 accumulation (~1e-5 per product)   */
+#define CIQ_F16X3   3   /* the same split in FP16 (lo parts scaled by 2^11),
+                           ~1e-6 per product; ciq_backward and the batched call
+                           return CIQ_ENOTSUP for both split forms               */
 
 #define CIQ_INVSQRT 0
 #define CIQ_SQRT    1

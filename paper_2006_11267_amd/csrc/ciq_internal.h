@@ -130,6 +130,8 @@ hipError_t launch_mvm_f64_rbf_iso(const MvmArgs& a, int nsb, int grid_x, hipStre
 hipError_t launch_mvm_f64_rbf_ard(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
 hipError_t launch_mvm_f64_m52_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
 hipError_t launch_mvm_f64_m52_ard(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
+hipError_t launch_mvm_x3_rbf(const MvmArgs& a, int nsb, int grid_x, bool half, hipStream_t st);
+hipError_t launch_mvm_x3_m52(const MvmArgs& a, int nsb, int grid_x, bool half, hipStream_t st);
 int mvm_rows_per_block(int dtype, int s, int rt);
 int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s);
 hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st);

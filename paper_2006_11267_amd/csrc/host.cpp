@@ -111,7 +111,7 @@ struct Sizer {
 // Point padding: the products are instantiated for 4/6/8/10/12/16 dims, the
 // gradient pass (dtype < 0) for 4/8/12/16.
 int pad_dims(int d, int dtype) {
-    if (dtype >= 0)
+    if (dtype == CIQ_F64 || dtype == CIQ_F32)
         return d <= 4 ? 4 : d <= 6 ? 6 : d <= 8 ? 8 : d <= 10 ? 10 : d <= 12 ? 12 : 16;
     return d <= 4 ? 4 : d <= 8 ? 8 : d <= 12 ? 12 : 16;
 }
@@ -418,8 +418,8 @@ struct Run {
 // product's input type; the timed launches write only the partial buffer.
 template <typename T>
 int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
-    const int nsb = (std::min(r.s, r.dtype == CIQ_F64 ? 64 : 128) + 15) / 16;
-    if (r.dtype != CIQ_F64 && nsb >= 8) {
+    const int nsb = (std::min(r.s, r.dtype == CIQ_F32 ? 128 : 64) + 15) / 16;
+    if ((r.dtype == CIQ_F32 && nsb >= 8) || r.dtype == CIQ_BF16X3 || r.dtype == CIQ_F16X3) {
         r.configure(1);
         return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
     }
@@ -936,7 +936,6 @@ int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double
 int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,
                    hipStream_t stream) {
     if (!valid_problem(p) || !valid_dtype(dtype) || !v || !y || s < 1 || ldv < s || ldy < s) return CIQ_EINVAL;
-    if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) return CIQ_ENOTSUP;
     const int dp = pad_dims(p->d, dtype);
     const size_t esz = (dtype == CIQ_F64) ? 8 : 4;
     const int rpb = mvm_rows_per_block(dtype, s, 2);
@@ -1060,8 +1059,8 @@ static int solve_single(const ciq_problem* p, const ciq_opts* o, const void* b, 
     const void* bp[1] = {b};
     void* op[1] = {out};
     if (o->dtype == CIQ_F64) return solve<double>(1, p, o, bp, s, ldb, op, ldo, solves, mode, info, stream);
-    if (o->dtype == CIQ_F32) return solve<float>(1, p, o, bp, s, ldb, op, ldo, solves, mode, info, stream);
-    return CIQ_ENOTSUP;
+    // F32 and the split forms: float inputs and outputs, FP64 vectors
+    return solve<float>(1, p, o, bp, s, ldb, op, ldo, solves, mode, info, stream);
 }
 
 int ciq_invsqrt_mvm(const ciq_problem* p, const ciq_opts* o, const void* b, int s, int ldb, void* out, int ldo,

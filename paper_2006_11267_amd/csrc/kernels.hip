@@ -20,6 +20,7 @@ namespace {
 
 int mvm_rows_per_block(int dtype, int s, int rt) {
     if (dtype == CIQ_F64) return 64 * rt;            // FP64 MFMA: column groups of <= 64
+    if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) return 64;
     const int nsb = (s > 128 ? 128 : s + 15) / 16;
     return (nsb <= 4 && rt == 2) ? 128 : 64;
 }
@@ -28,7 +29,7 @@ int mvm_rows_per_block(int dtype, int s, int rt) {
 // resident slots (256 CUs x blocks resident per CU, set by the kernel's
 // register use) with the least idle tail.
 int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s) {
-    const int cap = (dtype == CIQ_F64) ? 64 : 128;
+    const int cap = (dtype == CIQ_F32) ? 128 : 64;
     const int nsb = (s > cap ? cap : s + 15) / 16;
     const int per_cu = nsb <= 2 ? 4 : 2;
     const int slots = 256 * per_cu;
@@ -51,9 +52,10 @@ int mvm_pick_nsplit(int dtype, int nrb, int n_max, int s) {
 }
 
 hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
-    // Accumulators hold at most 8 (FP32) / 4 (FP64) column blocks of 16; wider
-    // right-hand sides run as column groups, each regenerating its entries.
-    const int cap = (dtype == CIQ_F64) ? 64 : 128;
+    // Accumulators hold at most 8 (FP32) / 4 (FP64, split forms) column blocks
+    // of 16; wider right-hand sides run as column groups, each regenerating its
+    // entries.
+    const int cap = (dtype == CIQ_F32) ? 128 : 64;
     for (int c0 = 0; c0 < a.s; c0 += cap) {
         MvmArgs g = a;
         g.s = (a.s - c0 < cap) ? a.s - c0 : cap;
@@ -63,6 +65,11 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
         if (dtype == CIQ_F64 && a.kt != nullptr) {
             g.v = static_cast<const double*>(a.v) + c0;
             e = launch_mvm_kt(g, nsb, st);
+        } else if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) {
+            g.v = static_cast<const float*>(a.v) + c0;
+            const bool half = (dtype == CIQ_F16X3);
+            e = (a.kernel == CIQ_KERNEL_RBF) ? launch_mvm_x3_rbf(g, nsb, a.nrb, half, st)
+                                              : launch_mvm_x3_m52(g, nsb, a.nrb, half, st);
         } else if (dtype == CIQ_F64) {
             g.v = static_cast<const double*>(a.v) + c0;
             if (a.kernel == CIQ_KERNEL_RBF)

@@ -214,6 +214,32 @@ def test_fp32_matches_fp64_oracle(kind, n, s, d):
         assert err < 1e-4, (mode, err, info["iters"])
 
 
+@pytest.mark.parametrize("prec,bar", [("bf16x3", 5e-3), ("f16x3", 5e-4)])
+def test_split_forms_against_exact(prec, bar):
+    """The split-operand BF16 / FP16 products inside a full CIQ solve: the
+    error against the exact K^{-1/2}B and K^{1/2}B (eigendecomposition) is
+    stated per form, bounded loosely here (kappa ~ 2e4)."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(21)
+    n, d, s = 2000, 6, 8
+    x = rng.random((n, d)).astype(np.float32)
+    b = rng.standard_normal((n, s)).astype(np.float32)
+    K = okern.kernel_matrix("matern52", x.astype(np.float64), [0.3], 1.0, 1e-2)
+    lam = np.linalg.eigvalsh(K)
+    bounds = (lam[0], lam[-1])
+    announce(f"ciq {prec} split form n={n} s={s}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), "matern52", [0.3], 1.0, 1e-2)
+    for mode, fn, pw in [("invsqrt", ciq.ciq_invsqrt_mvm, -0.5), ("sqrt", ciq.ciq_sqrt_mvm, 0.5)]:
+        out, info, _ = fn(prob, torch.from_numpy(b).cuda(), q=15, max_iter=3000, tol=1e-7, bounds=bounds,
+                          precision=prec)
+        exact = ociq.exact_power(K, b.astype(np.float64), pw)
+        err = colwise_rel(out.cpu().numpy(), exact).max()
+        print(f"{prec} {mode}: max rel err vs exact {err:.3e}, iters {info['iters']}", flush=True)
+        assert info["converged"]
+        assert err < bar, (mode, err)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_eig_bounds_match_oracle(prec):
     torch = torch_cuda()
