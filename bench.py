@@ -11,8 +11,12 @@ Accuracy: the metric counts columns delivered at relative error <= 1e-4. At
 this conditioning (kappa ~ 2.5e6) a MINRES stopping tolerance of 1e-4 leaves
 up to ~8e-4 error in K^{1/2}B, so the default stopping tolerance is 5e-6, and
 after the timed steps the run checks the last output's first 16 columns
-against the same path run to tol 1e-10 (untimed) and reports the error. The
-product runs on FP64 MFMA (FP32 entries alone cost ~1e-4 here).
+against the FP64 path run to tol 1e-10 (untimed) and reports the error.
+
+Default path: the kernel matrix is evaluated once per call in FP64, rounded
+to FP32 and kept resident in HBM (10 GB); every product streams it through
+FP32 MFMA with FP64 sums across 64-column chunks; Lanczos and search-direction
+vectors and all scalars are FP64 (dtype "f32" names the product arithmetic).
 
 Prints ONE JSON line (metric, value, roofline, cpu_baseline, ...).
 """
@@ -30,11 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}   # MI355X dense matrix peaks
-# HBM bytes per launch of the streamed resident-K product at this workload
+# HBM bytes per launch of the streamed resident-K products at this workload
 # (N = 50,000, S = 64): FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
-# runs of `bench.py --counters`, each scaled by the same counter's reading for
-# a plain 512 MiB device copy (profiles/mvm_kt_kernel_matern52_n50000_s64_hbm_traffic.md).
-KT_TRAFFIC_BYTES = 2.0711e10
+# runs of `bench.py --counters [--precision f64]`, each scaled by the same
+# counter's reading for a plain 512 MiB device copy
+# (profiles/mvm_kt*_kernel_matern52_n50000_s64_hbm_traffic.md).
+KT_TRAFFIC_BYTES = {"f64": 2.0711e10, "f32": 1.0260e10}
 METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
 
 
@@ -92,9 +97,9 @@ def main() -> int:
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
-    ap.add_argument("--precision", choices=["f64", "f32", "bf16x3", "f16x3"], default="f64",
-                    help="f64: FP64 MFMA product (meets 1e-4 at this conditioning); f32: FP32 MFMA product "
-                         "(~2e-4 at kappa 2.5e6); bf16x3 / f16x3: split-operand half-precision products")
+    ap.add_argument("--precision", choices=["f64", "f32", "bf16x3", "f16x3"], default="f32",
+                    help="f32: FP32 MFMA products of FP64 entries rounded once (resident K), FP64 vectors; "
+                         "f64: FP64 throughout; bf16x3 / f16x3: split-operand half-precision products")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -190,7 +195,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": args.precision,   # arithmetic of the dominant kernel (the product)
         "data": "synthetic",
         "config": {
             "workload": wl.name, "kernel": "matern52", "n": n, "d": p.d, "s": s, "q": q, "tol": tol,
@@ -202,8 +207,9 @@ def main() -> int:
         "roofline": {
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": (KT_TRAFFIC_BYTES if info["kernel_cached"] and (n, s) == (50000, 64) else None),
-            "kernel": ("mvm_kt_kernel" if info["kernel_cached"] else
+            "traffic": (KT_TRAFFIC_BYTES.get(args.precision) if info["kernel_cached"] and (n, s) == (50000, 64)
+                        else None),
+            "kernel": ({"f64": "mvm_kt_kernel", "f32": "mvm_kt32_kernel"}[args.precision] if info["kernel_cached"] else
                        {"f64": "mvm_f64mfma_kernel", "f32": "mvm_f32_kernel"}.get(args.precision, "mvm_x3_kernel")),
             "avg_ms": avg_ms, "launches": mvm_n,
         },

@@ -100,9 +100,10 @@ struct MvmArgs {
     const float* ps2;        // [nprob]
     const int* prob_done;    // [nprob] or nullptr
     const int* done;         // global done flag or nullptr
-    // resident kernel matrix (single FP64 problem): operand-tiled unit-scale
-    // entries, see mvm_cache.hip; nullptr = evaluate entries on the fly
-    const double* kt;
+    // resident kernel matrix (single problem): operand-tiled unit-scale
+    // entries, double (CIQ_F64) or float (CIQ_F32), see mvm_cache.hip;
+    // nullptr = evaluate entries on the fly
+    const void* kt;
     long long njs;           // padded columns / 4
 };
 
@@ -113,13 +114,18 @@ struct KBuildArgs {
     int n, dp, kernel, ard;
     int nchunk;              // padded columns / 64
     long long njs;           // padded columns / 4
-    double* kt;              // kcache_rows(n) x kcache_cols(n) doubles
+    int f32;                 // 1: store FP32 (entries evaluated in FP64, rounded once)
+    void* kt;                // kcache_rows(n) x kcache_cols(n) doubles or floats
 };
 size_t kcache_rows(int n);
 size_t kcache_cols(int n);
-size_t kcache_bytes(int n);
+size_t kcache_bytes(int n, int elem_bytes);
 hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st);
 hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st);
+hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st);
+// column blocks one product launch covers: 8 x 16 for the on-the-fly FP32
+// product, 4 x 16 otherwise
+inline int product_cap(int dtype, bool cached) { return (dtype == CIQ_F32 && !cached) ? 128 : 64; }
 
 // ---- launchers (kernels.hip, mvm_f32_*.hip) ---------------------------------
 hipError_t launch_mvm_f32_rbf_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);

@@ -193,7 +193,7 @@ struct Run {
     double* pscale = nullptr;  // [nprob][CIQ_MAX_D] FP32-product difference scales
     double* t = nullptr;
     double* w = nullptr;
-    const double* kt = nullptr;  // resident kernel matrix (single FP64 problem) or nullptr
+    const void* kt = nullptr;    // resident kernel matrix (single problem) or nullptr
     long long njs = 0;
     Dev d{};
     long long ysplit = 0;
@@ -252,7 +252,7 @@ struct Run {
         d.st = a.template take<IterState>(1);
     }
 
-    int rows_per_block() const { return mvm_rows_per_block(dtype, s, rt); }
+    int rows_per_block() const { return cached ? 64 * rt : mvm_rows_per_block(dtype, s, rt); }
 
     void configure(int rt_) {
         rt = rt_;
@@ -418,7 +418,7 @@ struct Run {
 // product's input type; the timed launches write only the partial buffer.
 template <typename T>
 int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
-    const int nsb = (std::min(r.s, r.dtype == CIQ_F32 ? 128 : 64) + 15) / 16;
+    const int nsb = (std::min(r.s, product_cap(r.dtype, r.cached)) + 15) / 16;
     if ((r.dtype == CIQ_F32 && nsb >= 8) || r.dtype == CIQ_BF16X3 || r.dtype == CIQ_F16X3) {
         r.configure(1);
         return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
@@ -512,7 +512,8 @@ void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob, int dty
 // Resident kernel matrix of one call: allocated after the decision in solve(),
 // freed when the call returns (after the device has drained its work).
 struct KCache {
-    double* ptr = nullptr;
+    void* ptr = nullptr;
+    int elem = 8;
     ~KCache() {
         if (ptr) {
             (void)hipDeviceSynchronize();
@@ -524,8 +525,9 @@ struct KCache {
 // Whether (and then where) a solve keeps K resident; CIQ_OK with *out = nullptr
 // means the products evaluate entries on the fly.
 int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* probs, KCache& kc) {
-    if (dtype != CIQ_F64 || nprob != 1 || o->kernel_cache == CIQ_CACHE_OFF) return CIQ_OK;
-    const size_t bytes = kcache_bytes(probs[0].n);
+    if ((dtype != CIQ_F64 && dtype != CIQ_F32) || nprob != 1 || o->kernel_cache == CIQ_CACHE_OFF) return CIQ_OK;
+    kc.elem = (dtype == CIQ_F64) ? 8 : 4;
+    const size_t bytes = kcache_bytes(probs[0].n, kc.elem);
     if (o->kernel_cache != CIQ_CACHE_ON) {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
@@ -619,6 +621,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         ka.ard = main.ard;
         ka.nchunk = (int)(kcache_cols(ka.n) / 64);
         ka.njs = (long long)(kcache_cols(ka.n) / 4);
+        ka.f32 = (kc.elem == 4) ? 1 : 0;
         ka.kt = kc.ptr;
         HIPCHK(launch_kbuild(ka, st));
         main.kt = bnd.kt = kc.ptr;

@@ -55,7 +55,7 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
     // Accumulators hold at most 8 (FP32) / 4 (FP64, split forms) column blocks
     // of 16; wider right-hand sides run as column groups, each regenerating its
     // entries.
-    const int cap = (dtype == CIQ_F32) ? 128 : 64;
+    const int cap = product_cap(dtype, a.kt != nullptr);
     for (int c0 = 0; c0 < a.s; c0 += cap) {
         MvmArgs g = a;
         g.s = (a.s - c0 < cap) ? a.s - c0 : cap;
@@ -65,6 +65,9 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
         if (dtype == CIQ_F64 && a.kt != nullptr) {
             g.v = static_cast<const double*>(a.v) + c0;
             e = launch_mvm_kt(g, nsb, st);
+        } else if (dtype == CIQ_F32 && a.kt != nullptr) {
+            g.v = static_cast<const float*>(a.v) + c0;
+            e = launch_mvm_kt32(g, nsb, st);
         } else if (dtype == CIQ_BF16X3 || dtype == CIQ_F16X3) {
             g.v = static_cast<const float*>(a.v) + c0;
             const bool half = (dtype == CIQ_F16X3);

@@ -18,17 +18,25 @@
 // contiguous memory (16-byte lanes stream measurably faster than 8-byte
 // ones). Rows are padded to a multiple of 128 and columns to a multiple of 64;
 // the padding holds finite entries of zero points, which meet zero rows of V.
+//
+// The FP32 path keeps the same entries rounded once to FP32 (10 GB at
+// N = 50,000) in the same order with four steps per 16-byte lane:
+//     kt32[((ib * (njs / 4) + js / 4) * 64 + lane) * 4 + js % 4],
+// and contracts them on v_mfma_f32_16x16x4_f32, whose A-operand lane layout
+// is the FP64 one. FP64 entries rounded once are ~10x more accurate than the
+// FP32 evaluation the on-the-fly FP32 product uses.
 #include "mvm_mfma.h"
 
 namespace ciq {
 namespace {
 
 using mfma::doublex4;
+using mfma::floatx4;
 typedef double doublex2 __attribute__((ext_vector_type(2)));
 
 // ---- build pass ------------------------------------------------------------
 // grid.x: 64-row blocks (one 16-row tile per wave), grid.y: column ranges.
-template <int KERNEL, int DP, bool ARD>
+template <int KERNEL, int DP, bool ARD, bool F32>
 __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
     constexpr int BN = 64;
     constexpr int XE = BN * DP;
@@ -48,7 +56,7 @@ __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
     const int nchunk = a.nchunk;
     const int c0 = (int)(((long long)blockIdx.y * nchunk) / gridDim.y);
     const int c1 = (int)(((long long)(blockIdx.y + 1) * nchunk) / gridDim.y);
-    doublex2* __restrict__ out = reinterpret_cast<doublex2*>(a.kt + (size_t)tile * a.njs * 64) + lane;
+    doublex2* __restrict__ out = reinterpret_cast<doublex2*>(static_cast<double*>(a.kt) + (size_t)tile * a.njs * 64) + lane;
     auto entry = [&](int jl) {
         double r2 = 0.0;
 #pragma unroll
@@ -64,6 +72,7 @@ __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
         if constexpr (!ARD) r2 *= sc0sq;
         return mfma::kentry64<KERNEL>(r2);
     };
+    floatx4* __restrict__ out32 = reinterpret_cast<floatx4*>(static_cast<float*>(a.kt) + (size_t)tile * a.njs * 64) + lane;
     for (int c = c0; c < c1; ++c) {
         __syncthreads();
         for (int e = tid; e < XE; e += 256) {
@@ -71,27 +80,42 @@ __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
             xs[e] = (j < n) ? a.xh[(long long)c * BN * DP + e] : 0.0;
         }
         __syncthreads();
+        if (F32) {
 #pragma unroll 2
-        for (int p = 0; p < 8; ++p) {
-            doublex2 kv;
-            kv[0] = entry(8 * p + (lane >> 4));
-            kv[1] = entry(8 * p + 4 + (lane >> 4));
-            __builtin_nontemporal_store(kv, out + (size_t)(c * 8 + p) * 64);
+            for (int p = 0; p < 4; ++p) {
+                floatx4 kv;
+#pragma unroll
+                for (int h = 0; h < 4; ++h) kv[h] = (float)entry(16 * p + 4 * h + (lane >> 4));
+                __builtin_nontemporal_store(kv, out32 + (size_t)(c * 4 + p) * 64);
+            }
+        } else {
+#pragma unroll 2
+            for (int p = 0; p < 8; ++p) {
+                doublex2 kv;
+                kv[0] = entry(8 * p + (lane >> 4));
+                kv[1] = entry(8 * p + 4 + (lane >> 4));
+                __builtin_nontemporal_store(kv, out + (size_t)(c * 8 + p) * 64);
+            }
         }
     }
 }
 
-template <int KERNEL, bool ARD>
+template <int KERNEL, bool ARD, bool F32>
 hipError_t launch_kbuild_dp(const KBuildArgs& a, dim3 grid, hipStream_t st) {
     switch (a.dp) {
-        case 4: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 4, ARD>), grid, dim3(256), 0, st, a); break;
-        case 6: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 6, ARD>), grid, dim3(256), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 8, ARD>), grid, dim3(256), 0, st, a); break;
-        case 10: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 10, ARD>), grid, dim3(256), 0, st, a); break;
-        case 12: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 12, ARD>), grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 16, ARD>), grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 4, ARD, F32>), grid, dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 6, ARD, F32>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 8, ARD, F32>), grid, dim3(256), 0, st, a); break;
+        case 10: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 10, ARD, F32>), grid, dim3(256), 0, st, a); break;
+        case 12: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 12, ARD, F32>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 16, ARD, F32>), grid, dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
+}
+
+template <int KERNEL, bool ARD>
+hipError_t launch_kbuild_t(const KBuildArgs& a, dim3 grid, hipStream_t st) {
+    return a.f32 ? launch_kbuild_dp<KERNEL, ARD, true>(a, grid, st) : launch_kbuild_dp<KERNEL, ARD, false>(a, grid, st);
 }
 
 // ---- streaming product -----------------------------------------------------
@@ -162,7 +186,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
     // operand loads: uniform base per (16-row tile, chunk), lane offset l + 64 st
     const double* kb[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) kb[rt] = a.kt + (size_t)(tile0 + rt) * a.njs * 64;
+    for (int rt = 0; rt < RT; ++rt) kb[rt] = static_cast<const double*>(a.kt) + (size_t)(tile0 + rt) * a.njs * 64;
     // KD chunks of operands in flight: chunk c + KD - 1 is requested while c
     // is contracted
     double kq[KD][RT][16];
@@ -235,6 +259,154 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
     }
 }
 
+// FP32 resident matrix (CIQ_F32): the same structure with FP32 operands and
+// MFMA, FP32 accumulation per 64-column chunk and FP64 across chunks.
+template <int NSB, int RT, int WAVES, int KD>
+__global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
+    constexpr int NT = 64 * WAVES;
+    constexpr int BN = 64;
+    constexpr int S16 = NSB * 16;
+    constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
+    constexpr int VPT = BN * S16 / NT;
+    constexpr int VROWS = NT / S16;
+    __shared__ float vs[BN * VST];
+
+    if (mfma::done_now(a.done)) return;
+    const int nsplit = a.nsplit;
+    const int split = (int)(blockIdx.x % (unsigned)nsplit);
+    const int rb = (int)(blockIdx.x / (unsigned)nsplit);
+    const int n = a.n;
+    const double o2 = a.o2, s2 = a.s2;
+    const float* __restrict__ v = static_cast<const float*>(a.v);
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: keeps bases in SGPRs
+    const int tile0 = (rb * WAVES + wave) * RT;
+    const int row0 = tile0 * 16;
+
+    const int nchunk = (n + BN - 1) / BN;
+    const int c0 = (int)(((long long)split * nchunk) / nsplit);
+    const int c1 = (int)(((long long)(split + 1) * nchunk) / nsplit);
+
+    // FP32 accumulation within a chunk, FP64 across chunks
+    floatx4 acc[RT][NSB];
+    double accd[RT][NSB][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) {
+            acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
+        }
+
+    // V staging: thread (vr, vc) moves rows vr + k * VROWS, column vc of the
+    // chunk. Chunks wholly inside the matrix with every column live take the
+    // unchecked path: a uniform base per row group plus one fixed per-lane
+    // offset, so the loads cost no vector ALU work.
+    const int vr = tid / S16, vc = tid - (tid / S16) * S16;
+    const unsigned voff = (unsigned)(vr * ldv + vc);
+    const bool full_cols = (s == S16);
+    float vreg[VPT];
+    auto fetch_v = [&](int c) {
+        const int j0 = c * BN;
+        if (full_cols && j0 + BN <= n) {
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) vreg[k] = (v + (size_t)(j0 + k * VROWS) * ldv)[voff];
+        } else {
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+                const int j = j0 + vr + k * VROWS;
+                vreg[k] = (vc < s && j < n) ? v[(size_t)j * ldv + vc] : 0.0f;
+            }
+        }
+    };
+    // operand loads: uniform base per (16-row tile, chunk), lane offset l + 64 st
+    const float* kb[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) kb[rt] = static_cast<const float*>(a.kt) + (size_t)(tile0 + rt) * a.njs * 64;
+    // KD chunks of operands in flight: chunk c + KD - 1 is requested while c
+    // is contracted
+    float kq[KD][RT][16];
+    auto fetch_k = [&](int c, float (&dst)[RT][16]) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const floatx4* base = reinterpret_cast<const floatx4*>(kb[rt] + (size_t)c * 1024);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const floatx4 x = __builtin_nontemporal_load(base + (unsigned)(lane + 64 * p));
+#pragma unroll
+                for (int h = 0; h < 4; ++h) dst[rt][4 * p + h] = x[h];
+            }
+        }
+    };
+    // one chunk: publish its V rows, start later loads, contract; the B
+    // operands of step st + 1 are read from LDS before step st's MFMAs
+    auto chunk = [&](int c, float (&cur)[RT][16], float (&far)[RT][16]) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
+        __syncthreads();
+        if (c + 1 < c1) fetch_v(c + 1);
+        if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
+        float bcur[NSB], bnxt[NSB];
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) bcur[sb] = vs[(lane >> 4) * VST + sb * 16 + (lane & 15)];
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            if (st + 1 < 16) {
+                const int jn = 4 * (st + 1) + (lane >> 4);
+#pragma unroll
+                for (int sb = 0; sb < NSB; ++sb) bnxt[sb] = vs[jn * VST + sb * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[rt][st], bcur[sb], acc[rt][sb], 0, 0, 0);
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb) bcur[sb] = bnxt[sb];
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[rt][sb][r];
+                acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+    if (c0 < c1) fetch_v(c0);
+#pragma unroll
+    for (int q = 0; q + 1 < KD; ++q)
+        if (c0 + q < c1) fetch_k(c0 + q, kq[q]);
+    // KD chunks per trip so the operand buffers rotate without copies
+    for (int c = c0; c < c1; c += KD) {
+#pragma unroll
+        for (int q = 0; q < KD; ++q)
+            if (c + q < c1) chunk(c + q, kq[q], kq[(q + KD - 1) % KD]);
+    }
+
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) {
+            const int cc = sb * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;   // FP32 16x16x4 layout
+                if (i < n && cc < s) {
+                    double val = o2 * accd[rt][sb][r];
+                    if (split == 0) val = fma(s2, (double)v[(long long)i * ldv + cc], val);
+                    y[(long long)i * ldy + cc] = val;
+                }
+            }
+        }
+    }
+}
+
 template <int NSB>
 hipError_t launch_kt_nsb(const MvmArgs& a, int grid, hipStream_t st) {
     if (a.rt == 1)
@@ -248,7 +420,7 @@ hipError_t launch_kt_nsb(const MvmArgs& a, int grid, hipStream_t st) {
 
 size_t kcache_rows(int n) { return ((size_t)n + 127) / 128 * 128; }
 size_t kcache_cols(int n) { return ((size_t)n + 63) / 64 * 64; }
-size_t kcache_bytes(int n) { return kcache_rows(n) * kcache_cols(n) * sizeof(double); }
+size_t kcache_bytes(int n, int elem_bytes) { return kcache_rows(n) * kcache_cols(n) * (size_t)elem_bytes; }
 
 hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st) {
     const int nrb64 = (int)(kcache_rows(a.n) / 64);
@@ -257,10 +429,19 @@ hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st) {
     while ((long long)nrb64 * ny < 4096 && ny < a.nchunk) ny *= 2;
     dim3 grid(nrb64, ny);
     if (a.kernel == CIQ_KERNEL_RBF)
-        return a.ard ? launch_kbuild_dp<CIQ_KERNEL_RBF, true>(a, grid, st)
-                     : launch_kbuild_dp<CIQ_KERNEL_RBF, false>(a, grid, st);
-    return a.ard ? launch_kbuild_dp<CIQ_KERNEL_MATERN52, true>(a, grid, st)
-                 : launch_kbuild_dp<CIQ_KERNEL_MATERN52, false>(a, grid, st);
+        return a.ard ? launch_kbuild_t<CIQ_KERNEL_RBF, true>(a, grid, st)
+                     : launch_kbuild_t<CIQ_KERNEL_RBF, false>(a, grid, st);
+    return a.ard ? launch_kbuild_t<CIQ_KERNEL_MATERN52, true>(a, grid, st)
+                 : launch_kbuild_t<CIQ_KERNEL_MATERN52, false>(a, grid, st);
+}
+
+template <int NSB>
+hipError_t launch_kt32_nsb(const MvmArgs& a, int grid, hipStream_t st) {
+    if (a.rt == 1)
+        hipLaunchKernelGGL((mvm_kt32_kernel<NSB, 1, 4, 2>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((mvm_kt32_kernel<NSB, 2, 4, 2>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
@@ -269,6 +450,15 @@ hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
         case 1: return launch_kt_nsb<1>(a, grid, st);
         case 2: return launch_kt_nsb<2>(a, grid, st);
         default: return launch_kt_nsb<4>(a, grid, st);
+    }
+}
+
+hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st) {
+    const int grid = a.nrb * a.nsplit;
+    switch (nsb) {
+        case 1: return launch_kt32_nsb<1>(a, grid, st);
+        case 2: return launch_kt32_nsb<2>(a, grid, st);
+        default: return launch_kt32_nsb<4>(a, grid, st);
     }
 }
 

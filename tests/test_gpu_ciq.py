@@ -172,7 +172,8 @@ def test_resident_matrix_small_j_parity(kind, n, s, d, ard):
 
 
 def test_kernel_cache_policy():
-    """auto keeps K only within the budget; the FP32 path never caches."""
+    """auto keeps K only within the budget; FP64 and FP32 cache, the split
+    forms never do."""
     torch = torch_cuda()
     ciq = ciq_module()
     rng = np.random.default_rng(5)
@@ -191,11 +192,16 @@ def test_kernel_cache_policy():
     p32 = ciq.Problem(torch.from_numpy(x.astype(np.float32)).cuda(), "rbf", [0.3], 1.0, 0.1)
     _, i32, _ = ciq.ciq_invsqrt_mvm(p32, bt.float(), q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
                                     kernel_cache="on")
-    assert not i32["kernel_cached"]
+    assert i32["kernel_cached"]
+    _, ix3, _ = ciq.ciq_invsqrt_mvm(p32, bt.float(), q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
+                                    kernel_cache="on", precision="bf16x3")
+    assert not ix3["kernel_cached"]
 
 
-@pytest.mark.parametrize("kind,n,s,d", [("matern52", 2000, 16, 6), ("rbf", 1500, 33, 8), ("rbf", 999, 64, 3)])
-def test_fp32_matches_fp64_oracle(kind, n, s, d):
+@pytest.mark.parametrize("cache", ["on", "off"])
+@pytest.mark.parametrize("kind,n,s,d", [("matern52", 2000, 16, 6), ("rbf", 1500, 33, 8), ("rbf", 999, 64, 3),
+                                        ("matern52", 4500, 64, 6)])
+def test_fp32_matches_fp64_oracle(kind, n, s, d, cache):
     torch = torch_cuda()
     ciq = ciq_module()
     rng = np.random.default_rng(n)
@@ -205,10 +211,12 @@ def test_fp32_matches_fp64_oracle(kind, n, s, d):
     K = okern.kernel_matrix(kind, x.astype(np.float64), ls, 1.0, 1e-2)
     lam = np.linalg.eigvalsh(K)
     bounds = (lam[0], lam[-1])
-    announce(f"ciq f32 {kind} n={n} s={s} d={d}")
+    announce(f"ciq f32 {kind} n={n} s={s} d={d} cache={cache}")
     prob = ciq.Problem(torch.from_numpy(x).cuda(), kind, ls, 1.0, 1e-2)
     for mode, fn in [("invsqrt", ciq.ciq_invsqrt_mvm), ("sqrt", ciq.ciq_sqrt_mvm)]:
-        out, info, _ = fn(prob, torch.from_numpy(b).cuda(), q=12, max_iter=1000, tol=1e-6, bounds=bounds)
+        out, info, _ = fn(prob, torch.from_numpy(b).cuda(), q=12, max_iter=1000, tol=1e-6, bounds=bounds,
+                          kernel_cache=cache)
+        assert info["kernel_cached"] == (cache == "on")
         ref, _ = ociq.ciq(lambda v: K @ v, b.astype(np.float64), bounds[0], bounds[1], 12, 1000, 1e-10, mode)
         err = colwise_rel(out.cpu().numpy(), ref).max()
         assert err < 1e-4, (mode, err, info["iters"])
