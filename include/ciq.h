@@ -112,7 +112,12 @@ typedef struct ciq_opts {
                                   dtypes and the batched call ignore this field.  */
     int32_t cache_budget_mib;  /* CIQ_CACHE_AUTO: largest matrix kept, in MiB
                                   (0: half of the free device memory at the call) */
-    int32_t reserved[4];
+    int32_t graph;             /* 1: capture two msMINRES iterations (all their
+                                  kernels) once in a HIP graph and replay it, one
+                                  launch per two iterations (small problems are
+                                  launch-bound); ignored with profile = 1. The
+                                  arithmetic is the same as without it.         */
+    int32_t reserved[3];
 } ciq_opts;
 
 /* Per-call report (host). Valid when the call returned CIQ_OK. */

@@ -51,7 +51,8 @@ class ciq_opts(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("kernel_cache", ctypes.c_int32),
         ("cache_budget_mib", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -348,9 +348,31 @@ struct Run {
         return a;
     }
 
+    // One msMINRES iteration's kernels (iteration j: the buffer roles depend
+    // on the parity of j only).
+    int enqueue_iteration(int j, hipStream_t st) {
+        double* qcur = qbuf[(j - 1) & 1];
+        double* qprv = qbuf[j & 1];
+        double* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
+        double* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
+        HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qcur, ypart), st));
+        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+        HIPCHK(launch_colsum(d, 0, st));
+        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+        HIPCHK(launch_colsum(d, 1, st));
+        HIPCHK(launch_scalar(d, st));
+        HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, q32, max_n,
+                                     st));
+        return CIQ_OK;
+    }
+
     // Krylov iterations after the start vectors are in qbuf[0]. Returns status.
+    // With use_graph, iterations (2k+1, 2k+2) are captured once into a HIP
+    // graph on a private stream and the graph is launched on `st` once per two
+    // iterations; kernels after the stop (or past max_iter) exit at once, so the
+    // replays are the same work as the eager loop.
     int iterate(hipStream_t st, int check_every, IterState* pinned, int* mvm_count,
-                hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed) {
+                hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed, bool use_graph = false) {
         // the state is reused scratch: clear `done` before the first kernel that reads it
         HIPCHK(launch_fill<int>(reinterpret_cast<int*>(d.st), sizeof(IterState) / sizeof(int), 0, st));
         HIPCHK(launch_dots<double>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
@@ -362,46 +384,81 @@ struct Run {
         }
         if (solves) HIPCHK(launch_fill<double>(solves, (size_t)rows_total * s * Q, 0.0, st));
         HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st));
-        int j = 1;
-        int pending = 0;
-        while (j <= max_iter) {
-            double* qcur = qbuf[(j - 1) & 1];
-            double* qprv = qbuf[j & 1];
-            double* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
-            double* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
-            const bool timed = ev_pool != nullptr && pending < n_ev;
-            if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
-            HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qcur, ypart), st));
-            if (timed) {
-                HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
-                ++pending;
-            }
-            HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
-            HIPCHK(launch_colsum(d, 0, st));
-            HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
-            HIPCHK(launch_colsum(d, 1, st));
-            HIPCHK(launch_scalar(d, st));
-            HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, q32,
-                                         max_n, st));
-            if (j % check_every == 0 || j == max_iter) {
-                HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                if (ev_pool) {
-                    // only launches issued while the run was still live count; the
-                    // device-side early exit after `done` is not a kernel product
-                    const int live = std::min(pending, pinned->iter - *mvm_timed);
-                    for (int k = 0; k < live; ++k) {
-                        float ms = 0.f;
-                        HIPCHK(hipEventElapsedTime(&ms, ev_pool[2 * k], ev_pool[2 * k + 1]));
-                        *mvm_ms += ms;
-                    }
-                    *mvm_timed += std::max(live, 0);
-                    pending = 0;
+        if (use_graph && ev_pool == nullptr) {
+            hipStream_t cs = nullptr;
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            struct Guard {
+                hipStream_t& cs;
+                hipGraph_t& g;
+                hipGraphExec_t& e;
+                ~Guard() {
+                    if (e) (void)hipGraphExecDestroy(e);
+                    if (g) (void)hipGraphDestroy(g);
+                    if (cs) (void)hipStreamDestroy(cs);
                 }
-                if (pinned->numeric) return CIQ_ENUMERIC;
-                if (pinned->done) break;
+            } guard{cs, graph, exec};
+            HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_iteration(1, cs);
+            if (rc == CIQ_OK) rc = enqueue_iteration(2, cs);
+            const hipError_t ec = hipStreamEndCapture(cs, &graph);
+            if (rc != CIQ_OK) return rc;
+            HIPCHK(ec);
+            HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            const int per_poll = std::max(1, check_every / 2);
+            int launched = 0;   // graph launches (2 iterations each)
+            while (2 * launched < max_iter) {
+                HIPCHK(hipGraphLaunch(exec, st));
+                ++launched;
+                if (launched % per_poll == 0 || 2 * launched >= max_iter) {
+                    HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    if (pinned->numeric) return CIQ_ENUMERIC;
+                    if (pinned->done) break;
+                }
             }
-            ++j;
+        } else {
+            int j = 1;
+            int pending = 0;
+            while (j <= max_iter) {
+                const bool timed = ev_pool != nullptr && pending < n_ev;
+                if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
+                HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qbuf[(j - 1) & 1], ypart),
+                                  st));
+                if (timed) {
+                    HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
+                    ++pending;
+                }
+                double* qcur = qbuf[(j - 1) & 1];
+                double* qprv = qbuf[j & 1];
+                HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+                HIPCHK(launch_colsum(d, 0, st));
+                HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+                HIPCHK(launch_colsum(d, 1, st));
+                HIPCHK(launch_scalar(d, st));
+                HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mbuf[(j - 1) & 1], mbuf[j & 1],
+                                             acc, solves, q32, max_n, st));
+                if (j % check_every == 0 || j == max_iter) {
+                    HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    if (ev_pool) {
+                        // only launches issued while the run was still live count; the
+                        // device-side early exit after `done` is not a kernel product
+                        const int live = std::min(pending, pinned->iter - *mvm_timed);
+                        for (int k = 0; k < live; ++k) {
+                            float ms = 0.f;
+                            HIPCHK(hipEventElapsedTime(&ms, ev_pool[2 * k], ev_pool[2 * k + 1]));
+                            *mvm_ms += ms;
+                        }
+                        *mvm_timed += std::max(live, 0);
+                        pending = 0;
+                    }
+                    if (pinned->numeric) return CIQ_ENUMERIC;
+                    if (pinned->done) break;
+                }
+                ++j;
+            }
         }
         HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -543,6 +600,28 @@ int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* p
     return CIQ_OK;
 }
 
+// Writes the resident matrix for the single problem of r and points r's
+// products at it.
+template <typename T>
+int kcache_build(Run<T>& r, const KCache& kc, hipStream_t st) {
+    if (!kc.ptr) return CIQ_OK;
+    KBuildArgs ka{};
+    ka.xh = r.xh;
+    for (int k = 0; k < CIQ_MAX_D; ++k) ka.scale[k] = r.h_scale[k];
+    ka.n = r.h_n[0];
+    ka.dp = r.dp;
+    ka.kernel = r.kernel;
+    ka.ard = r.ard;
+    ka.nchunk = (int)(kcache_cols(ka.n) / 64);
+    ka.njs = (long long)(kcache_cols(ka.n) / 4);
+    ka.f32 = (kc.elem == 4) ? 1 : 0;
+    ka.kt = kc.ptr;
+    HIPCHK(launch_kbuild(ka, st));
+    r.kt = kc.ptr;
+    r.njs = ka.njs;
+    return CIQ_OK;
+}
+
 struct ScratchLock {
     std::unique_lock<std::mutex> lk;
     explicit ScratchLock(int dev) : lk(g_scratch[dev].mu) {}
@@ -611,22 +690,9 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
 
     STCHK(main.upload_tables(st));
     STCHK(setup_points(main, probs, dtype, st));
-    if (kc.ptr) {
-        KBuildArgs ka{};
-        ka.xh = main.xh;
-        for (int k = 0; k < CIQ_MAX_D; ++k) ka.scale[k] = main.h_scale[k];
-        ka.n = main.h_n[0];
-        ka.dp = main.dp;
-        ka.kernel = main.kernel;
-        ka.ard = main.ard;
-        ka.nchunk = (int)(kcache_cols(ka.n) / 64);
-        ka.njs = (long long)(kcache_cols(ka.n) / 4);
-        ka.f32 = (kc.elem == 4) ? 1 : 0;
-        ka.kt = kc.ptr;
-        HIPCHK(launch_kbuild(ka, st));
-        main.kt = bnd.kt = kc.ptr;
-        main.njs = bnd.njs = ka.njs;
-    }
+    STCHK(kcache_build(main, kc, st));
+    bnd.kt = main.kt;
+    bnd.njs = main.njs;
 
     std::vector<double> lmin(nprob), lmax(nprob);
     int mvm_count = 0;
@@ -700,7 +766,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     }
 
     STCHK(main.iterate(st, check_every, pinned, &mvm_count, profile ? evs.data() : nullptr,
-                       profile ? check_every : 0, &mvm_ms, &mvm_timed));
+                       profile ? check_every : 0, &mvm_ms, &mvm_timed, o->graph == 1));
     const int iters = pinned->iter;
 
     // ---- combine -----------------------------------------------------------
@@ -799,6 +865,8 @@ int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const doubl
     const bool sqrt_mode = (mode == CIQ_SQRT);
     const bool want_hyper = dls || do2 || dnoise;
 
+    KCache kc;
+    STCHK(kcache_acquire(o, dtype, 1, p, kc));
     Run<T> r;
     fill_problem_tables(r, p, 1, dtype);
     r.dtype = dtype;
@@ -807,6 +875,7 @@ int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const doubl
     r.max_iter = o->max_iter;
     r.tol = o->tol;
     r.keep_solves = true;
+    r.cached = (kc.ptr != nullptr);
     r.plan(2);
 
     const int kpad = grad_k_pad((Q + (sqrt_mode ? 1 : 0)) * s);
@@ -833,6 +902,7 @@ int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const doubl
     r.fill_dev();
     STCHK(r.upload_tables(st));
     STCHK(setup_points(r, p, dtype, st));
+    STCHK(kcache_build(r, kc, st));
     HIPCHK(hipMemcpyAsync(r.t, t, Q * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(r.w, w, Q * sizeof(double), hipMemcpyHostToDevice, st));
 
@@ -888,6 +958,7 @@ int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const doubl
     info->q = Q;
     info->mvm_count = mvm_count;
     info->max_rel_residual = mr;
+    info->kernel_cached = (kc.ptr != nullptr) ? 1 : 0;
     for (int q = 0; q < Q; ++q) {
         info->t[q] = t[q];
         info->w[q] = w[q];

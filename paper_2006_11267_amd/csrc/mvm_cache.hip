@@ -444,7 +444,14 @@ hipError_t launch_kt32_nsb(const MvmArgs& a, int grid, hipStream_t st) {
     return hipGetLastError();
 }
 
+// the row blocks of a launch must stay inside the padded rows of the matrix
+static bool kt_rows_ok(const MvmArgs& a) {
+    return a.rt >= 1 && a.rt <= 2 && (size_t)a.nrb * 64 * a.rt <= kcache_rows(a.n) &&
+           (size_t)a.nrb * 64 * a.rt >= (size_t)a.n && a.njs * 4 == (long long)kcache_cols(a.n);
+}
+
 hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
+    if (!kt_rows_ok(a)) return hipErrorInvalidValue;
     const int grid = a.nrb * a.nsplit;
     switch (nsb) {
         case 1: return launch_kt_nsb<1>(a, grid, st);
@@ -454,6 +461,7 @@ hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
 }
 
 hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st) {
+    if (!kt_rows_ok(a)) return hipErrorInvalidValue;
     const int grid = a.nrb * a.nsplit;
     switch (nsb) {
         case 1: return launch_kt32_nsb<1>(a, grid, st);

@@ -54,7 +54,7 @@ class Problem:
 
 
 def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, check_every=0, profile=False,
-          kernel_cache="auto", cache_budget_mib=0):
+          kernel_cache="auto", cache_budget_mib=0, graph=False):
     o = L.ciq_opts()
     o.dtype = dtype_code
     o.q = int(q)
@@ -68,6 +68,7 @@ def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, ch
     o.profile = 1 if profile else 0
     o.kernel_cache = L.CACHE_MODES[kernel_cache]
     o.cache_budget_mib = int(cache_budget_mib)
+    o.graph = 1 if graph else 0
     return o
 
 
@@ -112,7 +113,7 @@ def ciq_eig_bounds(problem: Problem, steps: int = 20, v0: Optional[torch.Tensor]
 
 
 def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves, lanczos_steps, seed,
-           check_every, profile, kernel_cache, cache_budget_mib):
+           check_every, profile, kernel_cache, cache_budget_mib, graph):
     lib = L.load()
     code = _dtype_code(problem.x, precision)
     b2 = b if b.dim() == 2 else b.reshape(-1, 1)
@@ -123,7 +124,7 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
     solves = torch.empty((n, q, s), dtype=_elem_dtype(code), device=b.device) if keep_solves else None
     p, keep = problem.c_struct()
     o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, kernel_cache,
-              cache_budget_mib)
+              cache_budget_mib, graph)
     info = L.ciq_info()
     fn = getattr(lib, fn_name)
     L.check(fn(ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s, b2.stride(0),
@@ -137,24 +138,24 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
 def ciq_invsqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                     precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
                     lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
-                    kernel_cache: str = "auto", cache_budget_mib: int = 0):
+                    kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False):
     """K^{-1/2} B -> (out, info, solves or None)."""
     return _solve("ciq_invsqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph)
 
 
 def ciq_sqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                  precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
                  lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
-                 kernel_cache: str = "auto", cache_budget_mib: int = 0):
+                 kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False):
     """K^{1/2} B -> (out, info, solves or None)."""
     return _solve("ciq_sqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph)
 
 
 def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tensor], q: int = 12,
                             max_iter: int = 1000, tol: float = 1e-4, bounds=None, lanczos_steps: int = 0,
-                            seed: int = 0, check_every: int = 0, profile: bool = False):
+                            seed: int = 0, check_every: int = 0, profile: bool = False, graph: bool = False):
     """[K_p^{-1/2} B_p] for independent problems in one run -> (outs, infos)."""
     lib = L.load()
     P = len(problems)
@@ -170,7 +171,7 @@ def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tens
     bp = (ctypes.c_void_p * P)(*[b.data_ptr() for b in bcont])
     op = (ctypes.c_void_p * P)(*[o.data_ptr() for o in outs])
     infos = (L.ciq_info * P)()
-    o = _opts(L.CIQ_F32, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile)
+    o = _opts(L.CIQ_F32, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, graph=graph)
     L.check(lib.ciq_invsqrt_mvm_batched(P, parr, ctypes.byref(o), bp, s, op, infos, _stream()),
             "ciq_invsqrt_mvm_batched")
     del keeps
@@ -179,7 +180,7 @@ def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tens
 
 def ciq_backward(problem: Problem, g: torch.Tensor, t, w, solves: torch.Tensor, mode: str = "invsqrt",
                  max_iter: int = 200, tol: float = 1e-4, precision: Optional[str] = None, want_b: bool = True,
-                 want_hyper: bool = True, check_every: int = 0):
+                 want_hyper: bool = True, check_every: int = 0, kernel_cache: str = "auto"):
     """VJP of a forward call: returns (dB or None, dlengthscale, doutputscale, dnoise, info)."""
     lib = L.load()
     code = _dtype_code(problem.x, precision)
@@ -198,7 +199,7 @@ def ciq_backward(problem: Problem, g: torch.Tensor, t, w, solves: torch.Tensor, 
     do2 = ctypes.c_double()
     dn = ctypes.c_double()
     p, keep = problem.c_struct()
-    o = _opts(code, q, max_iter, tol, check_every=check_every)
+    o = _opts(code, q, max_iter, tol, check_every=check_every, kernel_cache=kernel_cache)
     info = L.ciq_info()
     mode_code = L.CIQ_SQRT if mode == "sqrt" else L.CIQ_INVSQRT
     sol = solves.contiguous()

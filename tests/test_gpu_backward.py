@@ -24,8 +24,8 @@ def _svgp_small(m=256, s=4, seed=5001, kind="rbf", ard=True, dtype=np.float64):
 
 @pytest.mark.parametrize("kind", ["rbf", "matern52"])
 @pytest.mark.parametrize("mode", ["invsqrt", "sqrt"])
-@pytest.mark.parametrize("ard", [True, False])
-def test_backward_fp64_matches_oracle(kind, mode, ard):
+@pytest.mark.parametrize("ard,cache", [(True, "on"), (False, "on"), (True, "off")])
+def test_backward_fp64_matches_oracle(kind, mode, ard, cache):
     torch = torch_cuda()
     ciq = ciq_module()
     x, b, g, ls = _svgp_small(kind=kind, ard=ard)
@@ -33,13 +33,14 @@ def test_backward_fp64_matches_oracle(kind, mode, ard):
     K = okern.kernel_matrix(kind, x, ls, o2, s2)
     lam = np.linalg.eigvalsh(K)
     bounds = (lam[0], lam[-1])
-    announce(f"backward f64 {kind} {mode} ard={ard} m={x.shape[0]}")
+    announce(f"backward f64 {kind} {mode} ard={ard} cache={cache} m={x.shape[0]}")
     prob = ciq.Problem(torch.from_numpy(x).cuda(), kind, ls, o2, s2)
     fn = ciq.ciq_sqrt_mvm if mode == "sqrt" else ciq.ciq_invsqrt_mvm
     out, info, solves = fn(prob, torch.from_numpy(b).cuda(), q=15, max_iter=1000, tol=1e-11, bounds=bounds,
                            keep_solves=True)
     db, dls, do2, dn, binfo = ciq.ciq_backward(prob, torch.from_numpy(g).cuda(), info["t"], info["w"], solves,
-                                               mode=mode, max_iter=1000, tol=1e-11)
+                                               mode=mode, max_iter=1000, tol=1e-11, kernel_cache=cache)
+    assert binfo["kernel_cached"] == (cache == "on")
     # oracle adjoint with its own forward solves
     mvm = lambda v: K @ v
     _, _, t, w, A = ociq.ciq(mvm, b, bounds[0], bounds[1], 15, 1000, 1e-11, mode, return_solves=True)
