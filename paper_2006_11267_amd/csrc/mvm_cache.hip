@@ -133,9 +133,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
     constexpr int BN = 64;
     constexpr int S16 = NSB * 16;
     constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
-    constexpr int VPT = BN * S16 / NT;
-    constexpr int VROWS = NT / S16;
-    __shared__ double vs[BN * VST];
+    __shared__ __attribute__((aligned(16))) double vs[BN * VST];
 
     if (mfma::done_now(a.done)) return;
     const int nsplit = a.nsplit;
@@ -162,24 +160,33 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
 #pragma unroll
         for (int sb = 0; sb < NSB; ++sb) acc[rt][sb] = doublex4{0.0, 0.0, 0.0, 0.0};
 
-    // V staging: thread (vr, vc) moves rows vr + k * VROWS, column vc of the
-    // chunk. Chunks wholly inside the matrix with every column live take the
-    // unchecked path: a uniform base per row group plus one fixed per-lane
-    // offset, so the loads cost no vector ALU work.
-    const int vr = tid / S16, vc = tid - (tid / S16) * S16;
-    const unsigned voff = (unsigned)(vr * ldv + vc);
-    const bool full_cols = (s == S16);
-    double vreg[VPT];
+    // thread (vr, vc) moves 2 consecutive columns vc*2.. of rows vr + k * VR:
+    // one 16-byte load and one 16-byte LDS store each; chunks wholly inside
+    // the matrix with every column live and 16-byte aligned rows take the
+    // unchecked path
+    constexpr int VW = 2;
+    using VecT = doublex2;
+    constexpr int CW = S16 / VW;
+    constexpr int VR = NT / CW;
+    constexpr int VPV = BN / VR;
+    const int vr = tid / CW, vc = tid - (tid / CW) * CW;
+    const bool vec_ok = (s == S16) && (ldv % VW == 0) && ((reinterpret_cast<uintptr_t>(v) & 15) == 0);
+    doublex2 vreg[VPV];
     auto fetch_v = [&](int c) {
         const int j0 = c * BN;
-        if (full_cols && j0 + BN <= n) {
+        if (vec_ok && j0 + BN <= n) {
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) vreg[k] = (v + (size_t)(j0 + k * VROWS) * ldv)[voff];
+            for (int k = 0; k < VPV; ++k)
+                vreg[k] = *reinterpret_cast<const doublex2*>(v + (size_t)(j0 + vr + k * VR) * ldv + VW * vc);
         } else {
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) {
-                const int j = j0 + vr + k * VROWS;
-                vreg[k] = (vc < s && j < n) ? v[(size_t)j * ldv + vc] : 0.0;
+            for (int k = 0; k < VPV; ++k) {
+                const int j = j0 + vr + k * VR;
+#pragma unroll
+                for (int h = 0; h < VW; ++h) {
+                    const int col = VW * vc + h;
+                    vreg[k][h] = (col < s && j < n) ? v[(size_t)j * ldv + col] : 0.0;
+                }
             }
         }
     };
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
     auto chunk = [&](int c, double (&cur)[RT][16], double (&far)[RT][16]) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
+        for (int k = 0; k < VPV; ++k) *reinterpret_cast<VecT*>(&vs[(vr + k * VR) * VST + VW * vc]) = vreg[k];
         __syncthreads();
         if (c + 1 < c1) fetch_v(c + 1);
         if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
@@ -267,9 +274,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
     constexpr int BN = 64;
     constexpr int S16 = NSB * 16;
     constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
-    constexpr int VPT = BN * S16 / NT;
-    constexpr int VROWS = NT / S16;
-    __shared__ float vs[BN * VST];
+    __shared__ __attribute__((aligned(16))) float vs[BN * VST];
 
     if (mfma::done_now(a.done)) return;
     const int nsplit = a.nsplit;
@@ -302,24 +307,33 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
             for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
         }
 
-    // V staging: thread (vr, vc) moves rows vr + k * VROWS, column vc of the
-    // chunk. Chunks wholly inside the matrix with every column live take the
-    // unchecked path: a uniform base per row group plus one fixed per-lane
-    // offset, so the loads cost no vector ALU work.
-    const int vr = tid / S16, vc = tid - (tid / S16) * S16;
-    const unsigned voff = (unsigned)(vr * ldv + vc);
-    const bool full_cols = (s == S16);
-    float vreg[VPT];
+    // thread (vr, vc) moves 4 consecutive columns vc*4.. of rows vr + k * VR:
+    // one 16-byte load and one 16-byte LDS store each; chunks wholly inside
+    // the matrix with every column live and 16-byte aligned rows take the
+    // unchecked path
+    constexpr int VW = 4;
+    using VecT = floatx4;
+    constexpr int CW = S16 / VW;
+    constexpr int VR = NT / CW;
+    constexpr int VPV = BN / VR;
+    const int vr = tid / CW, vc = tid - (tid / CW) * CW;
+    const bool vec_ok = (s == S16) && (ldv % VW == 0) && ((reinterpret_cast<uintptr_t>(v) & 15) == 0);
+    floatx4 vreg[VPV];
     auto fetch_v = [&](int c) {
         const int j0 = c * BN;
-        if (full_cols && j0 + BN <= n) {
+        if (vec_ok && j0 + BN <= n) {
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) vreg[k] = (v + (size_t)(j0 + k * VROWS) * ldv)[voff];
+            for (int k = 0; k < VPV; ++k)
+                vreg[k] = *reinterpret_cast<const floatx4*>(v + (size_t)(j0 + vr + k * VR) * ldv + VW * vc);
         } else {
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) {
-                const int j = j0 + vr + k * VROWS;
-                vreg[k] = (vc < s && j < n) ? v[(size_t)j * ldv + vc] : 0.0f;
+            for (int k = 0; k < VPV; ++k) {
+                const int j = j0 + vr + k * VR;
+#pragma unroll
+                for (int h = 0; h < VW; ++h) {
+                    const int col = VW * vc + h;
+                    vreg[k][h] = (col < s && j < n) ? v[(size_t)j * ldv + col] : 0.0f;
+                }
             }
         }
     };
@@ -347,7 +361,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
     auto chunk = [&](int c, float (&cur)[RT][16], float (&far)[RT][16]) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) vs[(vr + k * VROWS) * VST + vc] = vreg[k];
+        for (int k = 0; k < VPV; ++k) *reinterpret_cast<VecT*>(&vs[(vr + k * VR) * VST + VW * vc]) = vreg[k];
         __syncthreads();
         if (c + 1 < c1) fetch_v(c + 1);
         if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
