@@ -152,7 +152,7 @@ hipError_t launch_reduce_splits(const double* ypart, long long ysplit, int nspli
                                 int n, int s, TO* out, int ldo, hipStream_t st);
 
 template <typename T>
-hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q,
+hipError_t launch_dots(const Dev& d, T* y, long long ysplit, int nsplit, const T* q,
                        const T* qp, int phase, hipStream_t st);
 
 hipError_t launch_colsum(const Dev& d, int k, hipStream_t st);

@@ -356,13 +356,12 @@ struct Run {
         double* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
         double* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
         HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qcur, ypart), st));
-        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));   // also reduces the splits
         HIPCHK(launch_colsum(d, 0, st));
-        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+        HIPCHK(launch_dots<double>(d, ypart, ysplit, 1, qcur, qprv, 1, st));
         HIPCHK(launch_colsum(d, 1, st));
         HIPCHK(launch_scalar(d, st));
-        HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mprv, mcur, acc, solves, q32, max_n,
-                                     st));
+        HIPCHK(launch_update<double>(d, ypart, ysplit, 1, qcur, qprv, mprv, mcur, acc, solves, q32, max_n, st));
         return CIQ_OK;
     }
 
@@ -432,13 +431,13 @@ struct Run {
                 }
                 double* qcur = qbuf[(j - 1) & 1];
                 double* qprv = qbuf[j & 1];
-                HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));
+                HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));   // also reduces
                 HIPCHK(launch_colsum(d, 0, st));
-                HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 1, st));
+                HIPCHK(launch_dots<double>(d, ypart, ysplit, 1, qcur, qprv, 1, st));
                 HIPCHK(launch_colsum(d, 1, st));
                 HIPCHK(launch_scalar(d, st));
-                HIPCHK(launch_update<double>(d, ypart, ysplit, nsplit, qcur, qprv, mbuf[(j - 1) & 1], mbuf[j & 1],
-                                             acc, solves, q32, max_n, st));
+                HIPCHK(launch_update<double>(d, ypart, ysplit, 1, qcur, qprv, mbuf[(j - 1) & 1], mbuf[j & 1], acc,
+                                             solves, q32, max_n, st));
                 if (j % check_every == 0 || j == max_iter) {
                     HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));

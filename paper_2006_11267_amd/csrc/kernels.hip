@@ -151,9 +151,10 @@ template hipError_t launch_reduce_splits<double>(const double*, long long, int, 
 //   phase 1: alpha_j = sum of the phase-0 partials (fixed order),
 //            partial sums of ||Y - beta_j q_{j-1} - alpha_j q_j||^2 -> dots[..][1]
 //   init (phase 1 with q = q_prev = null): ||b||^2.
-// Y is the sum of the kernel product's split partials. Block: TS columns x RL
-// row lanes; grid (dots_blocks, ceil(s/TS), nprob); row lanes are combined in
-// a fixed order, so the result is deterministic.
+// Y is the sum of the kernel product's split partials; phase 0 writes that sum
+// over the first partial, so phase 1 and the update read one array. Block: TS
+// columns x RL row lanes; grid (dots_blocks, ceil(s/TS), nprob); row lanes are
+// combined in a fixed order, so the result is deterministic.
 // ----------------------------------------------------------------------------
 __host__ __device__ inline int col_tile(int s) {
     int ts = 1;
@@ -162,7 +163,7 @@ __host__ __device__ inline int col_tile(int s) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void dots_kernel(Dev d, const T* y, long long ysplit, int nsplit,
+__global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit, int nsplit,
                                                    const T* q, const T* qp, int phase) {
     __shared__ double sh[256];
     if (d.st->done) return;
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, const T* y, long long 
             const long long idx = (long long)(off + i) * s + c;
             double yv = (double)y[idx];
             for (int k = 1; k < nsplit; ++k) yv += (double)y[k * ysplit + idx];
+            if (nsplit > 1) y[idx] = (T)yv;          // the reduced product for phase 1 / update
             if (q == nullptr) {                       // ||b||^2
                 acc = fma(yv, yv, acc);
                 continue;
@@ -236,14 +238,14 @@ hipError_t launch_colsum(const Dev& d, int k, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_dots(const Dev& d, const T* y, long long ysplit, int nsplit, const T* q, const T* qp,
+hipError_t launch_dots(const Dev& d, T* y, long long ysplit, int nsplit, const T* q, const T* qp,
                        int phase, hipStream_t st) {
     const int TS = col_tile(d.s);
     dim3 grid(d.dots_blocks, (d.s + TS - 1) / TS, d.nprob);
     hipLaunchKernelGGL(dots_kernel<T>, grid, dim3(256), 0, st, d, y, ysplit, nsplit, q, qp, phase);
     return hipGetLastError();
 }
-template hipError_t launch_dots<double>(const Dev&, const double*, long long, int, const double*, const double*, int, hipStream_t);
+template hipError_t launch_dots<double>(const Dev&, double*, long long, int, const double*, const double*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Scalar stage (single block, FP64). Initial form: beta_1 = ||b||.
