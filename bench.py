@@ -81,6 +81,97 @@ def cpu_baseline(p, iters: int, q: int, sample_rows: int = 12288) -> dict:
     }
 
 
+def _rel(out, ref):
+    o = out.double().cpu().numpy()
+    r = ref.double().cpu().numpy()
+    e = np.linalg.norm(o - r, axis=0) / np.linalg.norm(r, axis=0)
+    return float(e.max()), float(np.median(e))
+
+
+def other_workload(args, torch, ciq, workloads) -> int:
+    """Secondary measurements on the other workloads (not the metric's line)."""
+    dev = torch.device("cuda:0")
+    if args.workload == 3:
+        wl = workloads.workload(3)
+        p = wl.problems[0]
+        tdt = torch.float64 if args.precision == "f64" else torch.float32
+        prec = None if args.precision in ("f64", "f32") else args.precision
+        x = torch.from_numpy(p.x).to(dev).to(tdt)
+        b = torch.from_numpy(p.b).to(dev).to(tdt)
+        prob = ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, info, _ = ciq.ciq_invsqrt_mvm(prob, b, q=wl.q, max_iter=wl.max_iter, tol=wl.tol, seed=3001,
+                                           precision=prec, profile=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"workload 3 {args.precision}: {dt:.1f} s, {info['iters']} iterations; FP64 reference ...")
+        k = 8
+        p64 = ciq.Problem(x.double().contiguous(), p.kernel, p.lengthscale, p.outputscale, p.noise)
+        ref, rinfo, _ = ciq.ciq_invsqrt_mvm(p64, b[:, :k].double().contiguous(), q=wl.q, max_iter=4000,
+                                            tol=1e-9, bounds=(info["lambda_min"], info["lambda_max"]))
+        emax, emed = _rel(out[:, :k], ref)
+        res = {"workload": wl.name, "mode": "invsqrt", "precision": args.precision, "n": p.n, "d": p.d, "s": p.s,
+               "q": wl.q, "tol": wl.tol, "lengthscales": [float(v) for v in p.lengthscale],
+               "columns_per_s": p.s / dt, "seconds": dt, "iters": info["iters"], "converged": info["converged"],
+               "kernel_cached": info["kernel_cached"], "mvm_ms": info["mvm_ms"] / max(info["mvm_timed"], 1),
+               "rel_err_vs_fp64_tol1e-10": {"max": emax, "median": emed, "columns": k,
+                                             "reference": "FP64 path, tol 1e-9",
+                                             "reference_iters": rinfo["iters"],
+                                             "reference_converged": rinfo["converged"]}}
+    elif args.workload == 4:
+        wl = workloads.workload(4)
+        probs = [ciq.Problem(torch.from_numpy(q.x).to(dev), q.kernel, q.lengthscale, q.outputscale, q.noise)
+                 for q in wl.problems]
+        bs = [torch.from_numpy(q.b).to(dev) for q in wl.problems]
+        kw = dict(q=wl.q, max_iter=wl.max_iter, tol=wl.tol)
+        ciq.ciq_invsqrt_mvm_batched(probs[:2], bs[:2], **kw)            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, infos = ciq.ciq_invsqrt_mvm_batched(probs, bs, **kw)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        log(f"workload 4 batched: {t_batch:.2f} s; 64 single calls ...")
+        t0 = time.perf_counter()
+        singles = [ciq.ciq_invsqrt_mvm(pr, bb, **kw) for pr, bb in zip(probs, bs)]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        cols = sum(bb.shape[1] for bb in bs)
+        gap = max(_rel(o, sgl[0])[0] for o, sgl in zip(outs, singles))
+        res = {"workload": wl.name, "problems": len(probs), "sum_n": int(sum(q.n for q in wl.problems)),
+               "s": wl.problems[0].s, "q": wl.q, "tol": wl.tol,
+               "batched": {"columns_per_s": cols / t_batch, "seconds": t_batch,
+                           "iters_max": max(i["iters"] for i in infos), "iters_min": min(i["iters"] for i in infos),
+                           "all_converged": all(i["converged"] for i in infos)},
+               "sequential_single_calls": {"columns_per_s": cols / t_seq, "seconds": t_seq},
+               "max_rel_gap_batched_vs_single": gap}
+    else:
+        wl = workloads.workload(5)
+        p = wl.problems[0]
+        x = torch.from_numpy(p.x).to(dev)
+        b = torch.from_numpy(p.b).to(dev)
+        g = torch.from_numpy(workloads.gaussian_rhs(p.n, p.s, 5006)).to(dev)
+        prob = ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise)
+        for rep in range(2):                                            # first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out, info, solves = ciq.ciq_invsqrt_mvm(prob, b, q=wl.q, max_iter=wl.max_iter, tol=wl.tol,
+                                                    keep_solves=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            db, dls, do2, dn, binfo = ciq.ciq_backward(prob, g, info["t"], info["w"], solves, mode="invsqrt",
+                                                       max_iter=wl.max_iter, tol=wl.tol)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        res = {"workload": wl.name, "m": p.n, "d": p.d, "s": p.s, "q": wl.q, "max_iter": wl.max_iter, "tol": wl.tol,
+               "forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+               "columns_per_s_forward_backward": p.s / (t2 - t0), "iters_forward": info["iters"],
+               "iters_backward": binfo["iters"], "kernel_cached": info["kernel_cached"],
+               "dlengthscale_norm": float(np.linalg.norm(dls)), "doutputscale": do2}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +188,10 @@ def main() -> int:
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
+    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5], default=2,
+                    help="2: the metric's workload (default). 3: RBF-ARD N=100,000 d=8 S=256 per precision form; "
+                         "4: 64 batched problems; 5: SVGP whitening forward + backward at M=5,000 "
+                         "(secondary measurements, one JSON line each)")
     ap.add_argument("--precision", choices=["f64", "f32", "bf16x3", "f16x3"], default="f32",
                     help="f32: FP32 MFMA products of FP64 entries rounded once (resident K), FP64 vectors; "
                          "f64: FP64 throughout; bf16x3 / f16x3: split-operand half-precision products")
@@ -108,6 +203,9 @@ def main() -> int:
     import torch
     import paper_2006_11267_amd as ciq
     import workloads
+
+    if args.workload != 2:
+        return other_workload(args, torch, ciq, workloads)
 
     wl = workloads.workload(2, n=args.n)
     p = wl.problems[0]
