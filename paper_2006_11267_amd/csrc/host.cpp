@@ -1,10 +1,12 @@
 // Host driver and C ABI of libciq.
 //
-// One solver call: validate -> scale/pad points on the device -> (optional)
-// Lanczos extreme-eigenvalue estimate -> HHT shifts/weights on the host ->
-// msMINRES loop (per iteration: kernel product, six-dot reduction, scalar
-// Givens stage, fused vector update; all queued on the caller's stream, the
-// host polls a device "done" flag every few iterations) -> combine.
+// One solver call: validate -> (optional) allocate and build the resident
+// kernel matrix -> scale/pad points on the device -> (optional) Lanczos
+// extreme-eigenvalue estimate -> HHT shifts/weights on the host -> msMINRES
+// loop (per iteration: kernel product, two-pass Lanczos inner products,
+// scalar Givens stage, fused vector update; all queued on the caller's
+// stream, optionally replayed from a HIP graph; the host polls a device
+// "done" flag every few iterations) -> combine.
 #include <algorithm>
 #include <chrono>
 #include <map>
