@@ -45,6 +45,8 @@ struct Dev {
     int bounds_mode;        // 1: plain Lanczos (no shifts), record T
     // dots
     int dots_blocks;        // partial blocks per problem
+    int fuse_sums;          // 1: consumers sum the dots partials themselves (few
+                            // blocks; saves the two column-sum launches)
     double* dots;           // [nprob][dots_blocks][s][2] (alpha, beta^2 partials)
     double* colsum;         // [2][ncol]: block-summed alpha, beta^2
     // column state

@@ -263,6 +263,7 @@ struct Run {
             while (ts < s && ts < 64) ts <<= 1;
             const int rows_per_pass = 256 / ts;
             d.dots_blocks = std::min(1024, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
+            d.fuse_sums = (d.dots_blocks <= 32) ? 1 : 0;
         }
         const int rpb = rows_per_block();
         nrb = 0;

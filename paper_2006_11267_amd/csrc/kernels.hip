@@ -162,6 +162,26 @@ __host__ __device__ inline int col_tile(int s) {
     return ts;
 }
 
+// Column sum k of the dots partials for global column g, in the fixed order of
+// colsum_kernel (lane r of 16 sums blocks r, r + 16, ...; then the lane sums in
+// order), so the fused and separate paths give bitwise equal results.
+__device__ inline double colsum_of(const Dev& d, int k, int g) {
+    const int p = g / d.s, c = g - p * d.s;
+    const double* base = d.dots + ((long long)p * d.dots_blocks * d.s + c) * 2 + k;
+    const long long stride = (long long)d.s * 2;
+    double t = 0.0;
+    for (int r = 0; r < 16; ++r) {
+        double acc = 0.0;
+        for (int b = r; b < d.dots_blocks; b += 16) acc += base[(long long)b * stride];
+        t += acc;
+    }
+    return t;
+}
+
+__device__ inline double colsum_get(const Dev& d, int k, int g) {
+    return d.fuse_sums ? colsum_of(d, k, g) : d.colsum[(long long)k * d.ncol + g];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit, int nsplit,
                                                    const T* q, const T* qp, int phase) {
@@ -176,7 +196,7 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit
     if (c < s) {
         const int g = p * s + c;
         const double bj = (q != nullptr) ? d.beta_cur[g] : 0.0;
-        const double al = (q != nullptr && phase == 1) ? d.colsum[g] : 0.0;
+        const double al = (q != nullptr && phase == 1) ? colsum_get(d, 0, g) : 0.0;
         for (int i = blockIdx.x * RL + rl; i < n; i += gridDim.x * RL) {
             const long long idx = (long long)(off + i) * s + c;
             double yv = (double)y[idx];
@@ -233,6 +253,7 @@ __global__ __launch_bounds__(1024) void colsum_kernel(Dev d, int k) {
 }
 
 hipError_t launch_colsum(const Dev& d, int k, hipStream_t st) {
+    if (d.fuse_sums) return hipSuccess;     // the consumers sum the partials themselves
     hipLaunchKernelGGL(colsum_kernel, dim3((d.ncol + 63) / 64), dim3(1024), 0, st, d, k);
     return hipGetLastError();
 }
@@ -256,7 +277,7 @@ __global__ __launch_bounds__(1024) void scalar_init_kernel(Dev d) {
     __syncthreads();
     const int ncol = d.ncol, Q = d.Q;
     for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
-        const double b1 = sqrt(d.colsum[(long long)d.ncol + g]);
+        const double b1 = sqrt(colsum_get(d, 1, g));
         const bool ok = (b1 > 0.0) && isfinite(b1);
         d.beta1[g] = ok ? b1 : 0.0;
         d.beta_cur[g] = 0.0;
@@ -318,8 +339,8 @@ __global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
     for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
         if (!d.colactive[g]) continue;
         const double bj = d.beta_cur[g];
-        double al = d.colsum[g];
-        double bn = sqrt(fmax(d.colsum[(long long)ncol + g], 0.0));
+        double al = colsum_get(d, 0, g);
+        double bn = sqrt(fmax(colsum_get(d, 1, g), 0.0));
         // ||K q_j|| ~ sqrt(alpha^2 + beta_j^2 + beta_{j+1}^2) scales the breakdown test
         bool broke = !(bn > d.bd_rtol * sqrt(al * al + bj * bj + bn * bn));
         if (!isfinite(al) || !isfinite(bn)) {

@@ -67,9 +67,9 @@ def test_graph_successive_solves_and_batched():
 
 def test_graph_loop_latency_workload1():
     """The first workload (N = 1024, S = 1, J = 100): report the time per
-    iteration of both loops (measured ~51 us for both: the seven dependent
-    kernels' device latency, not host launch cost, sets it); the graph loop
-    must not be slower."""
+    iteration of both loops (measured ~46 us for both: the dependent kernels'
+    device latency, not host launch cost, sets it); the graph loop must not
+    be slower."""
     torch = torch_cuda()
     ciq = ciq_module()
     import workloads
