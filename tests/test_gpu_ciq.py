@@ -142,11 +142,13 @@ def test_fp64_ragged_shapes(n, s, kind, q, cache):
 
 
 @pytest.mark.parametrize("kind,n,s,d,ard", [("matern52", 3001, 20, 5, True), ("rbf", 5000, 64, 8, False),
-                                            ("matern52", 4500, 64, 6, False), ("rbf", 700, 1, 12, True)])
+                                            ("matern52", 4500, 64, 6, False), ("rbf", 700, 1, 12, True),
+                                            ("rbf", 1200, 100, 3, False)])
 def test_resident_matrix_small_j_parity(kind, n, s, d, ard):
     """The streamed resident matrix against the oracle at fixed small J over
     tile-spanning ragged sizes, including the one-range-per-XCD split
-    (n >= 4096 rows, 64 columns) and single-column products. The bar is 10x
+    (n >= 4096 rows, 64 columns), single-column products and more than 64
+    columns (two column groups streaming the same matrix). The bar is 10x
     the oracle's own rounding spread (entries of K perturbed by one ulp), at
     least 1e-12."""
     torch = torch_cuda()
@@ -200,7 +202,7 @@ def test_kernel_cache_policy():
 
 @pytest.mark.parametrize("cache", ["on", "off"])
 @pytest.mark.parametrize("kind,n,s,d", [("matern52", 2000, 16, 6), ("rbf", 1500, 33, 8), ("rbf", 999, 64, 3),
-                                        ("matern52", 4500, 64, 6)])
+                                        ("matern52", 4500, 64, 6), ("rbf", 1100, 130, 4)])
 def test_fp32_matches_fp64_oracle(kind, n, s, d, cache):
     torch = torch_cuda()
     ciq = ciq_module()
