@@ -17,6 +17,9 @@ to Gaussian Processes and Bayesian Optimization", NeurIPS 2020):
                     the Lanczos + Givens-QR derivation of Appendix C.1.
 * ``ciq``        -- the CIQ composition (Sec. 3, Alg. S1) and the exact
                     eigendecomposition references.
+* ``precond``    -- the pivoted-Cholesky preconditioned form (Sec. 3.4,
+                    Appendix D): partial pivoted Cholesky, P^{-1} and P^{1/2}
+                    of P = Lbar Lbar^T + sigma^2 I, preconditioned CIQ.
 * ``adjoint``    -- the backward pass (Sec. 3.3) plus two independent
                     references: central finite differences and the
                     Daleckii-Krein divided-difference formula.

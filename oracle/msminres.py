@@ -37,6 +37,21 @@ value just reached); column s stops once all its shifts are frozen or its
 Lanczos run breaks down (beta_{j+1} <= breakdown_rtol ||K q_j||, an exact
 solve); everything stops after ``max_iter`` products with K. A zero column
 b_s gives x = 0 and counts as converged at once. The initial guess is zero.
+
+Preconditioned form (Appendix D; ``pinv`` = the map x -> P^{-1} x). The
+Lanczos process runs on A = P^{-1/2} K P^{-1/2} without forming P^{-1/2}:
+it keeps z_j = P^{1/2} qt_j and p_j = P^{-1} z_j = P^{-1/2} qt_j for the
+orthonormal Lanczos vectors qt_j of A started from P^{-1/2} b, so
+
+    v = K p_j - beta_j z_{j-1};  alpha_j = p_j^T v;  v -= alpha_j z_j
+    pt = P^{-1} v;  beta_{j+1} = sqrt(v^T pt);  z_{j+1} = v / beta_{j+1};  p_{j+1} = pt / beta_{j+1}
+
+(beta_1 = sqrt(b^T P^{-1} b)), the Givens stage is unchanged and the
+direction recurrence consumes p_j in place of q_j. Then
+x_j^{(q)} = P^{-1/2} y_j^{(q)} with y_j^{(q)} the MINRES iterate of
+(A + t_q I) y = P^{-1/2} b, and |phibar_{j+1}| is that system's residual.
+The breakdown test uses sqrt(alpha_j^2 + beta_j^2 + beta_{j+1}^2), the
+A-norm of A qt_j, in place of ||K q_j||.
 """
 from __future__ import annotations
 
@@ -56,8 +71,9 @@ class MinresInfo:
 
 
 def msminres(mvm, B: np.ndarray, shifts, max_iter: int, tol: float,
-             breakdown_rtol: float = 1e-13):
-    """Returns X with X[q] ~= (K + t_q I)^{-1} B, and a MinresInfo."""
+             breakdown_rtol: float = 1e-13, pinv=None):
+    """Returns X with X[q] ~= (K + t_q I)^{-1} B, and a MinresInfo. With
+    ``pinv``, X[q] ~= P^{-1/2} (A + t_q I)^{-1} P^{-1/2} B (see the header)."""
     B = np.asarray(B, dtype=np.float64)
     squeeze = B.ndim == 1
     if squeeze:
@@ -66,7 +82,11 @@ def msminres(mvm, B: np.ndarray, shifts, max_iter: int, tol: float,
     N, S = B.shape
     Qn = t.size
 
-    beta1 = np.linalg.norm(B, axis=0)                 # ||b_s||
+    if pinv is None:
+        beta1 = np.linalg.norm(B, axis=0)             # ||b_s||
+    else:
+        PB = pinv(B)
+        beta1 = np.sqrt(np.maximum(np.sum(B * PB, axis=0), 0.0))
     X = np.zeros((Qn, N, S))
     m1 = np.zeros((Qn, N, S))                          # m_{j-1}
     m2 = np.zeros((Qn, N, S))                          # m_{j-2}
@@ -74,6 +94,11 @@ def msminres(mvm, B: np.ndarray, shifts, max_iter: int, tol: float,
     q = np.zeros_like(B)
     q[:, nz] = B[:, nz] / beta1[nz]
     q_prev = np.zeros_like(B)
+    if pinv is not None:                               # p_j = P^{-1} z_j (q holds z_j)
+        pq = np.zeros_like(B)
+        pq[:, nz] = PB[:, nz] / beta1[nz]
+    else:
+        pq = q
     beta_j = np.zeros(S)                               # beta_j (0 for j = 1)
 
     c1 = np.ones((Qn, S)); s1 = np.zeros((Qn, S))      # G_{j-1}
@@ -91,12 +116,18 @@ def msminres(mvm, B: np.ndarray, shifts, max_iter: int, tol: float,
         if not active.any():
             break
         iters += 1
-        y = mvm(q)                                     # K q_j (all columns share it)
+        y = mvm(pq)                                    # K q_j (all columns share it)
         v = y - beta_j * q_prev
-        alpha = np.sum(q * v, axis=0)
+        alpha = np.sum(pq * v, axis=0)
         v = v - alpha * q
-        beta_next = np.linalg.norm(v, axis=0)
-        broke = beta_next <= breakdown_rtol * np.linalg.norm(y, axis=0)
+        if pinv is None:
+            beta_next = np.linalg.norm(v, axis=0)
+            scale = np.linalg.norm(y, axis=0)
+        else:
+            pv = pinv(v)
+            beta_next = np.sqrt(np.maximum(np.sum(v * pv, axis=0), 0.0))
+            scale = np.sqrt(alpha ** 2 + beta_j ** 2 + beta_next ** 2)
+        broke = beta_next <= breakdown_rtol * scale
         beta_next = np.where(broke, 0.0, beta_next)
         alphas.append(alpha.copy())
         betas.append(beta_next.copy())
@@ -112,7 +143,7 @@ def msminres(mvm, B: np.ndarray, shifts, max_iter: int, tol: float,
         tau = c * phibar
         phibar_next = -s * phibar
 
-        m = (q[None] - delta[:, None, :] * m1 - eps[:, None, :] * m2) / gamma[:, None, :]
+        m = (pq[None] - delta[:, None, :] * m1 - eps[:, None, :] * m2) / gamma[:, None, :]
         upd = active[None, :] & ~frozen                # (Q, S) shifts still moving
         X += np.where(upd[:, None, :], tau[:, None, :] * m, 0.0)
 
@@ -134,6 +165,12 @@ def msminres(mvm, B: np.ndarray, shifts, max_iter: int, tol: float,
         qn[:, cont] = v[:, cont] / beta_next[cont]
         q_prev = np.where(cont[None, :], q, q_prev)
         q = np.where(cont[None, :], qn, q)
+        if pinv is None:
+            pq = q
+        else:
+            pn = np.zeros_like(q)
+            pn[:, cont] = pv[:, cont] / beta_next[cont]
+            pq = np.where(cont[None, :], pn, pq)
         beta_j = np.where(cont, beta_next, beta_j)
         frozen = frozen | (broke & active)[None, :]
         active = cont
