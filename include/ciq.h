@@ -11,8 +11,11 @@
  * approximation of Sec. 3 (K^{-1/2} ~= sum_q w_q (t_q I + K)^{-1}), the
  * Hale-Higham-Trefethen shifts/weights of Appendix B (Alg. S2) and one
  * multi-shift MINRES run (Appendix C, Alg. S4) whose Lanczos recurrence shares
- * a single on-the-fly kernel product K V per iteration across all Q shifts.
- * K is never stored: every product regenerates its entries from X.
+ * a single kernel product K V per iteration across all Q shifts. Products
+ * regenerate K's entries from X, or stream a copy of K that the call writes
+ * once and frees (ciq_opts.kernel_cache). An optional pivoted-Cholesky
+ * preconditioner (Sec. 3.4, Appendix D; ciq_opts.precond_rank) gives results
+ * equal to K^{+-1/2} B up to an orthogonal rotation in fewer iterations.
  *
  * Conventions shared by every entry point:
  *  - Status: every call returns CIQ_OK (0) or one of the CIQ_E* codes below;
@@ -74,6 +77,7 @@ extern "C" {
 
 #define CIQ_MAX_Q   64   /* quadrature points                                       */
 #define CIQ_MAX_D   16   /* input dimensions                                        */
+#define CIQ_MAX_RANK 1024 /* preconditioner rank                                    */
 
 /* One kernel matrix K = outputscale * k(X, X) + noise * I. */
 typedef struct ciq_problem {
@@ -101,15 +105,16 @@ typedef struct ciq_opts {
     int32_t check_every;       /* iterations between host convergence polls (0: auto) */
     int32_t profile;           /* 1: time every kernel-product launch of the msMINRES
                                   loop with HIP events on `stream` (ciq_info.mvm_ms) */
-    int32_t kernel_cache;      /* CIQ_CACHE_*. Single-problem CIQ_F64 solves may write
-                                  the unit-scale entries k(x_i, x_j) once per call
-                                  into a device buffer of kcache bytes
-                                  (ceil(n/128)*128 x ceil(n/64)*64 doubles, 20 GB at
-                                  n = 50,000) and stream them in every product
-                                  instead of re-evaluating them; the buffer is
-                                  allocated and freed inside the call. Results are
-                                  the same products up to summation order. Other
-                                  dtypes and the batched call ignore this field.  */
+    int32_t kernel_cache;      /* CIQ_CACHE_*. Single-problem CIQ_F64 / CIQ_F32 solves
+                                  (and ciq_backward) may write the unit-scale entries
+                                  k(x_i, x_j) once per call into a device buffer of
+                                  ceil(n/128)*128 x ceil(n/64)*64 doubles (CIQ_F64,
+                                  20 GB at n = 50,000) or floats (CIQ_F32, entries
+                                  evaluated in FP64 and rounded once) and stream
+                                  them in every product instead of re-evaluating
+                                  them; the buffer is allocated and freed inside
+                                  the call. The split forms and the batched call
+                                  ignore this field.                             */
     int32_t cache_budget_mib;  /* CIQ_CACHE_AUTO: largest matrix kept, in MiB
                                   (0: half of the free device memory at the call) */
     int32_t graph;             /* 1: capture two msMINRES iterations (all their
@@ -117,7 +122,24 @@ typedef struct ciq_opts {
                                   launch per two iterations (small problems are
                                   launch-bound); ignored with profile = 1. The
                                   arithmetic is the same as without it.         */
-    int32_t reserved[3];
+    int32_t precond_rank;      /* R > 0: pivoted-Cholesky preconditioned msMINRES-CIQ
+                                  (Sec. 3.4, Appendix D), single-problem calls only,
+                                  needs noise > 0, R <= CIQ_MAX_RANK (clamped to n).
+                                  P = Lbar Lbar^T + sigma^2 I with Lbar the rank-R
+                                  factor of ciq_pivoted_cholesky; the solves run on
+                                  P^{-1/2} K P^{-1/2} (P^{-1} by the inversion lemma,
+                                  P^{1/2} B in closed form from the eigenvalues of
+                                  Lbar^T Lbar), and the outputs are
+                                    invsqrt: R' B = P^{-1/2} (P^{-1/2} K P^{-1/2})^{-1/2} B
+                                    sqrt:    R B = K R' B
+                                  with R' R'^T = K^{-1} and R R^T = K: K^{-1/2} B and
+                                  K^{1/2} B up to an orthogonal rotation (the same
+                                  rotation for every column), not those matrices
+                                  themselves. The eigenvalue bounds, tol and
+                                  max_rel_residual refer to the preconditioned
+                                  system. 0: plain CIQ. ciq_backward and the batched
+                                  call return CIQ_ENOTSUP for R > 0.             */
+    int32_t reserved[2];
 } ciq_opts;
 
 /* Per-call report (host). Valid when the call returned CIQ_OK. */
@@ -135,6 +157,9 @@ typedef struct ciq_info {
                                   kernel-product launches (ms), else 0             */
     int32_t mvm_timed;         /* number of launches in mvm_ms                     */
     int32_t kernel_cached;     /* 1 if the products streamed a resident K           */
+    int32_t precond_rank;      /* pivots the preconditioner's factor took (<= R), 0
+                                  without preconditioning                           */
+    double precond_trace;      /* trace of o^2 k(X, X) - Lbar Lbar^T (0 without)    */
 } ciq_info;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -225,6 +250,26 @@ int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double
 int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts* o,
                             const void* const* b, int s, void* const* out,
                             ciq_info* infos, hipStream_t stream);
+
+/*
+ * Rank-`rank` partial pivoted Cholesky factor of the noise-free kernel matrix
+ * Ktil = outputscale * k(X, X), the preconditioner factor of Appendix D
+ * (greedy rule of Harbrecht, Peters and Schneider 2012): step m takes the row p
+ * with the largest residual diagonal d_p (ties: the smaller row), sets
+ *   Lbar[i][m] = (Ktil[i][p] - sum_{k<m} Lbar[i][k] Lbar[p][k]) / sqrt(d_p)
+ * for rows not yet chosen (sqrt(d_p) at p, 0 at earlier pivots) and lowers
+ * d_i by Lbar[i][m]^2. It stops early once the largest residual diagonal is
+ * <= 1e-10 * outputscale (numerical rank reached); later columns are 0.
+ * Entries and sums in FP64 from the points converted to FP64.
+ *   dtype: element type of X (CIQ_F64: double; any other dtype: float).
+ *   l_out: device, n x rank doubles, row-major (ld = rank), overwritten.
+ *   piv_out: host, rank ints, the row chosen at each step (-1 after a stop).
+ *   trace_out: host, nullable: trace of Ktil - Lbar Lbar^T at the end.
+ * Synchronous. Errors: CIQ_EINVAL (problem, dtype, pointers, rank < 1 or
+ * rank > min(n, CIQ_MAX_RANK)), CIQ_ENOMEM, CIQ_EHIP.
+ */
+int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out,
+                         int* piv_out, double* trace_out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@ CIQ_CACHE_AUTO, CIQ_CACHE_OFF, CIQ_CACHE_ON = 0, 1, 2
 CACHE_MODES = {"auto": CIQ_CACHE_AUTO, "off": CIQ_CACHE_OFF, "on": CIQ_CACHE_ON}
 CIQ_MAX_Q = 64
 CIQ_MAX_D = 16
+CIQ_MAX_RANK = 1024
 
 KERNELS = {"rbf": CIQ_KERNEL_RBF, "matern52": CIQ_KERNEL_MATERN52}
 DTYPES = {"f64": CIQ_F64, "f32": CIQ_F32, "bf16x3": CIQ_BF16X3, "f16x3": CIQ_F16X3}
@@ -52,7 +53,8 @@ class ciq_opts(ctypes.Structure):
         ("kernel_cache", ctypes.c_int32),
         ("cache_budget_mib", ctypes.c_int32),
         ("graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("precond_rank", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -70,6 +72,8 @@ class ciq_info(ctypes.Structure):
         ("mvm_ms", ctypes.c_double),
         ("mvm_timed", ctypes.c_int32),
         ("kernel_cached", ctypes.c_int32),
+        ("precond_rank", ctypes.c_int32),
+        ("precond_trace", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -87,6 +91,8 @@ class ciq_info(ctypes.Structure):
             "mvm_ms": self.mvm_ms,
             "mvm_timed": self.mvm_timed,
             "kernel_cached": bool(self.kernel_cached),
+            "precond_rank": self.precond_rank,
+            "precond_trace": self.precond_trace,
         }
 
 
@@ -110,6 +116,8 @@ PROTOTYPES = {
     "ciq_invsqrt_mvm_batched": (_I, [_I, ctypes.POINTER(ciq_problem), ctypes.POINTER(ciq_opts),
                                      ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP),
                                      ctypes.POINTER(ciq_info), _VP]),
+    "ciq_pivoted_cholesky": (_I, [ctypes.POINTER(ciq_problem), _I, _I, _VP, ctypes.POINTER(ctypes.c_int), _PD,
+                                  _VP]),
 }
 
 _lib = None

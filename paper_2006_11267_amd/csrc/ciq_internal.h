@@ -162,14 +162,20 @@ hipError_t launch_scalar_init(const Dev& d, hipStream_t st);
 hipError_t launch_scalar(const Dev& d, hipStream_t st);
 
 // q32 (nullable): FP32 copy of the next Lanczos vector, the FP32 product's operand
+// pnext (nullable): preconditioned form. Then y holds the finished direction
+// w (not the product), the direction recurrence consumes qcur = p_j, a
+// continuing column gets qprev <- w / beta_{j+1} (z_{j+1}) and
+// pnext <- pnext / beta_{j+1} (p_{j+1} = P^{-1} z_{j+1}), and q32 copies pnext.
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur,
                          T* qprev, const T* m_prev, T* m_cur, T* acc, T* solves, float* q32,
-                         int max_n, hipStream_t st);
+                         int max_n, hipStream_t st, T* pnext = nullptr);
 
+// pvec (nullable): preconditioned start, pvec <- pvec / beta_1 too and q32
+// copies pvec instead of q.
 template <typename T>
 hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows,
-                               hipStream_t st);
+                               hipStream_t st, T* pvec = nullptr);
 
 template <typename TI, typename TO>
 hipError_t launch_copy(const TI* src, int ld_src, int n, int s, TO* dst, int ld_dst,
@@ -180,6 +186,56 @@ hipError_t launch_fill(T* p, size_t count, T value, hipStream_t st);
 
 template <typename T>
 hipError_t launch_splitmix(T* v, int n, uint64_t seed, int ld, hipStream_t st);
+
+// ---- pivoted-Cholesky preconditioner (precond.hip) ---------------------------
+// Partial pivoted Cholesky of Ktil = o^2 k(X, X): step m reads the pivot the
+// previous pick chose, writes column m of L and updates the residual diagonal;
+// the pick reduces the per-block (largest residual diagonal, smallest row)
+// candidates and the residual trace.
+struct PcholArgs {
+    const double* xh;        // n x dp FP64 points (raw coordinates)
+    double scale[CIQ_MAX_D]; // per-dimension scale of coordinate differences
+    int n, dp, kernel, ard;
+    double o2;               // outputscale (the diagonal of Ktil)
+    double stop_abs;         // stop once the largest residual diagonal <= this
+    double* L;               // n x ldl, row-major; column m written at step m
+    int ldl;
+    double* dres;            // [n] residual diagonal
+    int* chosen;             // [n] 1 once the row was a pivot
+    int* piv;                // [rank + 1] pivot of step m (-1: stopped)
+    double* pval;            // [rank + 1] residual diagonal of that pivot
+    double* trace;           // [rank + 1] residual trace before step m
+    double* bval;            // [nblk] block candidates
+    int* bidx;
+    double* bsum;
+    int nblk;
+};
+hipError_t launch_pchol_init(const PcholArgs& a, hipStream_t st);
+hipError_t launch_pchol_pick(const PcholArgs& a, int m, hipStream_t st);
+hipError_t launch_pchol_col(const PcholArgs& a, int m, hipStream_t st);
+
+// Low-rank pieces of P^{-1} x and P^{1/2} x (both alpha0 x + U f(U^T x)):
+//   part[c][r][s] = sum_{i in chunk c} A[i][r] X[i][s]                (lr_part)
+//   T[r][s] = f_r * sum_c part[c][r][s]   (f nullable: 1)             (lr_reduce)
+//   Y[i][s] = alpha0 X[i][s] + sum_r A[i][r] T[r][s]  (X nullable: 0), (lr_apply)
+//     optionally dotp[blk][s] = sum over the block's rows of X[i][s] Y[i][s]
+//     and, with colmask, columns whose mask is 0 left untouched (dotp 0).
+// `done` (nullable): skip the launch's work once the run has stopped.
+int lr_part_chunks(int n, int R, int S);
+hipError_t launch_lr_part(const double* A, int lda, const double* X, int ldx, int n, int R, int S,
+                          int nchunk, double* part, const int* done, hipStream_t st);
+hipError_t launch_lr_reduce(const double* part, int nchunk, int R, int S, const double* f, double* T,
+                            int ldt, const int* done, hipStream_t st);
+int lr_apply_blocks(int n);
+hipError_t launch_lr_apply(double alpha0, const double* X, int ldx, const double* A, int lda,
+                           const double* T, int ldt, int n, int R, int S, double* Y, int ldy,
+                           double* dotp, const int* colmask, const int* done, hipStream_t st);
+// out[c] = sum_b dotp[b][c] (fixed order), b < nblk
+hipError_t launch_lr_dotsum(const double* dotp, int nblk, int S, double* out, const int* done,
+                            hipStream_t st);
+// Preconditioned Lanczos direction: y <- (y - beta_j z_prev) - alpha_j z_cur
+// (alpha_j from colsum[0..ncol)), in place.
+hipError_t launch_pc_w(const Dev& d, double* y, const double* zc, const double* zp, hipStream_t st);
 
 // ---- backward tile pass (grad.hip) ------------------------------------------
 int grad_rows_pad(int n);

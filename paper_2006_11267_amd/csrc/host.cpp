@@ -23,6 +23,7 @@ namespace ciq {
 int hht_quadrature(double lmin, double lmax, int Q, double* t, double* w);
 void bounds_from_tridiag(int J, const double* alpha, const double* beta, double noise, double* lmin,
                          double* lmax);
+void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& evals, std::vector<double>& v);
 }  // namespace ciq
 
 using namespace ciq;
@@ -165,6 +166,178 @@ int get_device(int* dev) {
     return CIQ_OK;
 }
 
+// ---- pivoted-Cholesky preconditioner (Sec. 3.4, Appendix D) -----------------
+// P = Lbar Lbar^T + sigma^2 I; with Lbar^T Lbar = V diag(lam) V^T and
+// U = Lbar V, P^{-1} x and P^{1/2} x are alpha0 x + U diag(f) U^T x (see
+// precond.hip). Built once per call in a device allocation of its own.
+constexpr double kPcholStopRtol = 1e-10;   // numerical-rank stop of the factorisation
+
+struct DevAlloc {
+    void* p = nullptr;
+    ~DevAlloc() {
+        if (p) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+        }
+    }
+};
+
+// Bump allocation inside one device buffer (256-byte aligned pieces).
+template <typename T>
+T* carve(char* base, size_t& off, size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+}
+
+struct Precond {
+    int R = 0;              // columns of U (requested rank, at most n)
+    int rank = 0;           // pivots the factorisation took
+    double s2 = 0.0;        // sigma^2
+    double trace = 0.0;     // trace of Ktil - Lbar Lbar^T
+    double* U = nullptr;    // n x R
+    double* fin = nullptr;  // [R] weights of P^{-1}
+    double* fsq = nullptr;  // [R] weights of P^{1/2}
+    double* part = nullptr; // low-rank partials
+    double* T = nullptr;    // R x max(s, R)
+    double* dotp = nullptr; // [apply blocks][s]
+    DevAlloc mem;
+};
+
+int pchol_blocks(int n) { return std::max(1, std::min((n + 255) / 256, 2048)); }
+
+// Scratch of one factorisation (L itself is the caller's).
+struct PcholScratch {
+    double *dres, *pval, *trace, *bval, *bsum;
+    int *chosen, *piv, *bidx;
+};
+template <typename F>
+void pchol_layout(int n, int R, F&& take_d, PcholScratch& w) {
+    const int nblk = pchol_blocks(n);
+    w.dres = take_d((size_t)n);
+    w.pval = take_d((size_t)R + 1);
+    w.trace = take_d((size_t)R + 1);
+    w.bval = take_d((size_t)nblk);
+    w.bsum = take_d((size_t)nblk);
+    // integer arrays as doubles' worth of space (8 bytes per entry)
+    w.chosen = reinterpret_cast<int*>(take_d((size_t)n));
+    w.piv = reinterpret_cast<int*>(take_d((size_t)R + 1));
+    w.bidx = reinterpret_cast<int*>(take_d((size_t)nblk));
+}
+
+// Rank-R factor into L (n x ldl, zero-filled here); pivots and the final
+// residual trace to the host. Synchronous.
+int pchol_run(const double* xh, int n, int dp, int kernel, int ard, const double* scale, double o2, int R,
+              double* L, int ldl, const PcholScratch& w, std::vector<int>& piv, double* trace, hipStream_t st) {
+    PcholArgs a{};
+    a.xh = xh;
+    for (int k = 0; k < CIQ_MAX_D; ++k) a.scale[k] = scale[k];
+    a.n = n;
+    a.dp = dp;
+    a.kernel = kernel;
+    a.ard = ard;
+    a.o2 = o2;
+    a.stop_abs = kPcholStopRtol * o2;
+    a.L = L;
+    a.ldl = ldl;
+    a.dres = w.dres;
+    a.chosen = w.chosen;
+    a.piv = w.piv;
+    a.pval = w.pval;
+    a.trace = w.trace;
+    a.bval = w.bval;
+    a.bidx = w.bidx;
+    a.bsum = w.bsum;
+    a.nblk = pchol_blocks(n);
+    HIPCHK(launch_fill<double>(L, (size_t)n * ldl, 0.0, st));
+    HIPCHK(launch_pchol_init(a, st));
+    for (int m = 0; m < R; ++m) {
+        HIPCHK(launch_pchol_pick(a, m, st));
+        HIPCHK(launch_pchol_col(a, m, st));
+    }
+    HIPCHK(launch_pchol_pick(a, R, st));
+    piv.assign((size_t)R, -1);
+    HIPCHK(hipMemcpyAsync(piv.data(), w.piv, (size_t)R * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(trace, w.trace + R, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CIQ_OK;
+}
+
+// Y = alpha0 X + U diag(f) U^T X for X, Y n x S (ld S; Y may be X).
+int pc_apply(const Precond& pc, double alpha0, const double* f, const double* X, int n, int S, double* Y,
+             double* dotp, const int* colmask, const int* done, hipStream_t st) {
+    const int nch = lr_part_chunks(n, pc.R, S);
+    HIPCHK(launch_lr_part(pc.U, pc.R, X, S, n, pc.R, S, nch, pc.part, done, st));
+    HIPCHK(launch_lr_reduce(pc.part, nch, pc.R, S, f, pc.T, S, done, st));
+    HIPCHK(launch_lr_apply(alpha0, X, S, pc.U, pc.R, pc.T, S, n, pc.R, S, Y, S, dotp, colmask, done, st));
+    return CIQ_OK;
+}
+
+// Factorisation, Gram matrix, its eigendecomposition (host, cyclic Jacobi)
+// and U = Lbar V for one problem whose FP64 points are xh (n x dp).
+int pc_build(const ciq_problem& p, const double* xh, int dp, int kernel, int ard, const double* scale, int rank,
+             int s_cap, Precond& pc, hipStream_t st) {
+    const int n = p.n;
+    const int R = std::min(rank, n);
+    pc.R = R;
+    pc.s2 = p.noise;
+    // partial buffer for the widths it serves: s_cap (solve), 1 (bounds), R (Gram)
+    size_t part_n = 0;
+    for (int w : {s_cap, 1, R}) part_n = std::max(part_n, (size_t)lr_part_chunks(n, R, w) * R * w);
+    size_t off = 0;
+    PcholScratch w{};
+    auto layout = [&](char* base) {
+        off = 0;
+        pc.U = carve<double>(base, off, (size_t)n * R);
+        double* L = carve<double>(base, off, (size_t)n * R);
+        pc.fin = carve<double>(base, off, R);
+        pc.fsq = carve<double>(base, off, R);
+        pc.part = carve<double>(base, off, part_n);
+        pc.T = carve<double>(base, off, (size_t)R * std::max(s_cap, R));
+        pc.dotp = carve<double>(base, off, (size_t)lr_apply_blocks(n) * s_cap);
+        pchol_layout(n, R, [&](size_t c) { return carve<double>(base, off, c); }, w);
+        return L;
+    };
+    layout(nullptr);
+    if (hipMalloc(&pc.mem.p, off) != hipSuccess) {
+        (void)hipGetLastError();
+        pc.mem.p = nullptr;
+        return CIQ_ENOMEM;
+    }
+    double* L = layout(static_cast<char*>(pc.mem.p));
+    std::vector<int> piv;
+    STCHK(pchol_run(xh, n, dp, kernel, ard, scale, p.outputscale, R, L, R, w, piv, &pc.trace, st));
+    pc.rank = 0;
+    for (int v : piv) pc.rank += (v >= 0) ? 1 : 0;
+    // Gram matrix Lbar^T Lbar (R x R) and its eigendecomposition
+    const int nch = lr_part_chunks(n, R, R);
+    HIPCHK(launch_lr_part(L, R, L, R, n, R, R, nch, pc.part, nullptr, st));
+    HIPCHK(launch_lr_reduce(pc.part, nch, R, R, nullptr, pc.T, R, nullptr, st));
+    std::vector<double> G((size_t)R * R), lam, V;
+    HIPCHK(hipMemcpyAsync(G.data(), pc.T, G.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < R; ++i)
+        for (int j = i + 1; j < R; ++j) {
+            const double m = 0.5 * (G[(size_t)i * R + j] + G[(size_t)j * R + i]);
+            G[(size_t)i * R + j] = G[(size_t)j * R + i] = m;
+        }
+    sym_eig_jacobi(R, G, lam, V);
+    std::vector<double> fin(R), fsq(R);
+    const double s2 = p.noise, sg = std::sqrt(p.noise);
+    for (int r = 0; r < R; ++r) {
+        const double l = std::max(lam[r], 0.0);
+        fin[r] = -1.0 / (s2 * (l + s2));
+        fsq[r] = 1.0 / (std::sqrt(l + s2) + sg);
+    }
+    HIPCHK(hipMemcpyAsync(pc.T, V.data(), V.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(pc.fin, fin.data(), R * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(pc.fsq, fsq.data(), R * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_lr_apply(0.0, nullptr, 0, L, R, pc.T, R, n, R, R, pc.U, R, nullptr, nullptr, nullptr, st));
+    HIPCHK(hipStreamSynchronize(st));   // host vectors are pageable and short-lived
+    return CIQ_OK;
+}
+
 // ---------------------------------------------------------------------------
 // One Krylov run over nprob problems (the single-problem calls use nprob = 1).
 // ---------------------------------------------------------------------------
@@ -177,6 +350,8 @@ struct Run {
     int nsplit = 1, nrb = 0, rt = 2, nsplit_alloc = 1, nrb_alloc = 1;
     bool keep_solves = false;
     bool cached = false;   // products stream a resident kernel matrix (kt)
+    bool precond = false;  // preconditioned run (single problem): Lanczos in the P^{-1} inner product
+    const Precond* pc = nullptr;
     // device memory: points in FP64, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
     // consumes an FP32 copy q32 of the current Lanczos vector)
@@ -187,6 +362,7 @@ struct Run {
     double* acc = nullptr;
     double* solves = nullptr;  // [rows][Q][s]
     float* q32 = nullptr;      // FP32 product operand (T = float only)
+    double* pbuf[2] = {nullptr, nullptr};  // preconditioned: p_j = P^{-1} z_j (qbuf holds z_j)
     WorkItem* wl = nullptr;
     int* pn = nullptr;
     int* poff = nullptr;
@@ -221,6 +397,10 @@ struct Run {
         acc = a.template take<double>(vec);
         if (keep_solves) solves = a.template take<double>(vec * Q);
         if (sizeof(T) == 4) q32 = a.template take<float>(vec);
+        if (precond) {
+            pbuf[0] = a.template take<double>(vec);
+            pbuf[1] = a.template take<double>(vec);
+        }
         wl = a.template take<WorkItem>(std::max(nrb_alloc, 1));
         pn = a.template take<int>(nprob);
         poff = a.template take<int>(nprob);
@@ -263,7 +443,9 @@ struct Run {
             while (ts < s && ts < 64) ts <<= 1;
             const int rows_per_pass = 256 / ts;
             d.dots_blocks = std::min(1024, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
-            d.fuse_sums = (d.dots_blocks <= 32) ? 1 : 0;
+            // the preconditioned step reads the block-summed alpha (colsum) and
+            // writes beta^2 there itself
+            d.fuse_sums = (d.dots_blocks <= 32 && !precond) ? 1 : 0;
         }
         const int rpb = rows_per_block();
         nrb = 0;
@@ -351,14 +533,37 @@ struct Run {
         return a;
     }
 
-    // One msMINRES iteration's kernels (iteration j: the buffer roles depend
-    // on the parity of j only).
-    int enqueue_iteration(int j, hipStream_t st) {
+    // Operand of iteration j's kernel product: q_j (p_j when preconditioned),
+    // or its FP32 copy.
+    const void* operand(int j) const {
+        if (q32) return q32;
+        return precond ? pbuf[(j - 1) & 1] : qbuf[(j - 1) & 1];
+    }
+
+    // Iteration j's kernels after the product (the buffer roles depend on the
+    // parity of j only).
+    int enqueue_post(int j, hipStream_t st) {
         double* qcur = qbuf[(j - 1) & 1];
         double* qprv = qbuf[j & 1];
         double* mcur = mbuf[j & 1];       // holds m_{j-2}, receives m_j
         double* mprv = mbuf[(j - 1) & 1];  // holds m_{j-1}
-        HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qcur, ypart), st));
+        if (precond) {
+            // Appendix D: alpha_j = p_j^T (K p_j - beta_j z_{j-1}),
+            // w = K p_j - beta_j z_{j-1} - alpha_j z_j, P^{-1} w, beta_{j+1}^2 = w^T P^{-1} w
+            double* pcur = pbuf[(j - 1) & 1];
+            double* pnxt = pbuf[j & 1];
+            const int* done = &d.st->done;
+            HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, pcur, qprv, 0, st));   // also reduces
+            HIPCHK(launch_colsum(d, 0, st));
+            HIPCHK(launch_pc_w(d, ypart, qcur, qprv, st));
+            STCHK(pc_apply(*pc, 1.0 / pc->s2, pc->fin, ypart, rows_total, s, pnxt, pc->dotp, d.colactive, done,
+                           st));
+            HIPCHK(launch_lr_dotsum(pc->dotp, lr_apply_blocks(rows_total), s, d.colsum + d.ncol, done, st));
+            HIPCHK(launch_scalar(d, st));
+            HIPCHK(launch_update<double>(d, ypart, ysplit, 1, pcur, qprv, mprv, mcur, acc, solves, q32, max_n, st,
+                                         pnxt));
+            return CIQ_OK;
+        }
         HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));   // also reduces the splits
         HIPCHK(launch_colsum(d, 0, st));
         HIPCHK(launch_dots<double>(d, ypart, ysplit, 1, qcur, qprv, 1, st));
@@ -366,6 +571,12 @@ struct Run {
         HIPCHK(launch_scalar(d, st));
         HIPCHK(launch_update<double>(d, ypart, ysplit, 1, qcur, qprv, mprv, mcur, acc, solves, q32, max_n, st));
         return CIQ_OK;
+    }
+
+    // One msMINRES iteration's kernels.
+    int enqueue_iteration(int j, hipStream_t st) {
+        HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
+        return enqueue_post(j, st);
     }
 
     // Krylov iterations after the start vectors are in qbuf[0]. Returns status.
@@ -377,15 +588,23 @@ struct Run {
                 hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed, bool use_graph = false) {
         // the state is reused scratch: clear `done` before the first kernel that reads it
         HIPCHK(launch_fill<int>(reinterpret_cast<int*>(d.st), sizeof(IterState) / sizeof(int), 0, st));
-        HIPCHK(launch_dots<double>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
-        HIPCHK(launch_colsum(d, 1, st));
+        if (precond) {
+            // start z_1 = c / beta_1, p_1 = P^{-1} c / beta_1, beta_1^2 = c^T P^{-1} c
+            STCHK(pc_apply(*pc, 1.0 / pc->s2, pc->fin, qbuf[0], rows_total, s, pbuf[0], pc->dotp, nullptr, nullptr,
+                           st));
+            HIPCHK(launch_lr_dotsum(pc->dotp, lr_apply_blocks(rows_total), s, d.colsum + d.ncol, nullptr, st));
+        } else {
+            HIPCHK(launch_dots<double>(d, qbuf[0], 0, 1, nullptr, nullptr, 1, st));
+            HIPCHK(launch_colsum(d, 1, st));
+        }
         HIPCHK(launch_scalar_init(d, st));
         if (Q > 0) {
             HIPCHK(launch_fill<double>(mbuf[0], (size_t)rows_total * s * Q, 0.0, st));
             HIPCHK(launch_fill<double>(mbuf[1], (size_t)rows_total * s * Q, 0.0, st));
         }
         if (solves) HIPCHK(launch_fill<double>(solves, (size_t)rows_total * s * Q, 0.0, st));
-        HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st));
+        HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st,
+                                           precond ? pbuf[0] : nullptr));
         if (use_graph && ev_pool == nullptr) {
             hipStream_t cs = nullptr;
             hipGraph_t graph = nullptr;
@@ -426,21 +645,12 @@ struct Run {
             while (j <= max_iter) {
                 const bool timed = ev_pool != nullptr && pending < n_ev;
                 if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
-                HIPCHK(launch_mvm(dtype, mvm_args(q32 ? static_cast<const void*>(q32) : qbuf[(j - 1) & 1], ypart),
-                                  st));
+                HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
                 if (timed) {
                     HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
                     ++pending;
                 }
-                double* qcur = qbuf[(j - 1) & 1];
-                double* qprv = qbuf[j & 1];
-                HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));   // also reduces
-                HIPCHK(launch_colsum(d, 0, st));
-                HIPCHK(launch_dots<double>(d, ypart, ysplit, 1, qcur, qprv, 1, st));
-                HIPCHK(launch_colsum(d, 1, st));
-                HIPCHK(launch_scalar(d, st));
-                HIPCHK(launch_update<double>(d, ypart, ysplit, 1, qcur, qprv, mbuf[(j - 1) & 1], mbuf[j & 1], acc,
-                                             solves, q32, max_n, st));
+                STCHK(enqueue_post(j, st));
                 if (j % check_every == 0 || j == max_iter) {
                     HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));
@@ -646,11 +856,14 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
 
     KCache kc;
     STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
+    const bool precond = o->precond_rank > 0;
+    Precond pc;
 
     // ---- sizing: bounds run (s = 1, Q = 0) and main run share the points ----
     Run<T> main;
     fill_problem_tables(main, probs, nprob, dtype);
     main.cached = (kc.ptr != nullptr);
+    main.precond = precond;
     main.dtype = dtype;
     main.s = s;
     main.Q = o->q;
@@ -668,6 +881,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     bnd.tol = 0.0;
     bnd.bounds_mode = 1;
     bnd.cached = main.cached;
+    bnd.precond = precond;
     bnd.plan(2);
 
     Sizer sz;
@@ -695,6 +909,12 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     STCHK(kcache_build(main, kc, st));
     bnd.kt = main.kt;
     bnd.njs = main.njs;
+    if (precond) {
+        STCHK(pc_build(probs[0], main.xh, main.dp, main.kernel, main.ard, main.h_scale.data(), o->precond_rank, s,
+                       pc, st));
+        main.pc = &pc;
+        bnd.pc = &pc;
+    }
 
     std::vector<double> lmin(nprob), lmax(nprob);
     int mvm_count = 0;
@@ -739,7 +959,8 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
                 al[j] = Th[((size_t)j * nprob + p) * 2 + 0];
                 be[j] = Th[((size_t)j * nprob + p) * 2 + 1];
             }
-            bounds_from_tridiag(Jp, al.data(), be.data(), probs[p].noise, &lmin[p], &lmax[p]);
+            // floor of the spectrum: sigma^2 for K, 1 for P^{-1/2} K P^{-1/2}
+            bounds_from_tridiag(Jp, al.data(), be.data(), precond ? 1.0 : probs[p].noise, &lmin[p], &lmax[p]);
             if (!(lmin[p] > 0.0) || !(lmax[p] >= lmin[p]) || !std::isfinite(lmax[p])) return CIQ_ENUMERIC;
         }
         // the bounds run reused the scratch after the points; restore the main tables
@@ -760,6 +981,9 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         HIPCHK((launch_copy<T, double>(static_cast<const T*>(b_ptrs[p]), ldb, main.h_n[p], s,
                                        main.qbuf[0] + (size_t)main.h_off[p] * s, s, st)));
     HIPCHK(hipStreamSynchronize(st));  // th/wh are pageable host vectors
+    if (precond)   // start vectors C = P^{1/2} B (Appendix D), in place
+        STCHK(pc_apply(pc, std::sqrt(pc.s2), pc.fsq, main.qbuf[0], main.rows_total, s, main.qbuf[0], nullptr, nullptr,
+                       nullptr, st));
     if (main.q32) {
         HIPCHK((launch_copy<double, float>(main.qbuf[0], s, main.rows_total, s, main.q32, s, st)));
         STCHK(tune_rt(main, main.q32, st));
@@ -835,6 +1059,8 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         in.mvm_ms = mvm_ms;
         in.mvm_timed = mvm_timed;
         in.kernel_cached = (kc.ptr != nullptr) ? 1 : 0;
+        in.precond_rank = precond ? pc.rank : 0;
+        in.precond_trace = precond ? pc.trace : 0.0;
     }
     return CIQ_OK;
 }
@@ -847,6 +1073,8 @@ int check_solve_args(const ciq_problem* p, const ciq_opts* o, const void* b, int
     if (o->q < 1 || o->q > CIQ_MAX_Q || o->max_iter < 1) return CIQ_EINVAL;
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return CIQ_EINVAL;
     if (o->lanczos_steps < 0 || o->check_every < 0) return CIQ_EINVAL;
+    if (o->precond_rank < 0 || o->precond_rank > CIQ_MAX_RANK) return CIQ_EINVAL;
+    if (o->precond_rank > 0 && !(p->noise > 0.0)) return CIQ_EINVAL;   // P = Lbar Lbar^T + sigma^2 I
     return CIQ_OK;
 }
 
@@ -1157,7 +1385,7 @@ int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts*
         if (rc != CIQ_OK) return rc;
         if (probs[p].kernel != probs[0].kernel) return CIQ_EINVAL;
     }
-    if (o->dtype != CIQ_F32) return CIQ_ENOTSUP;
+    if (o->dtype != CIQ_F32 || o->precond_rank != 0) return CIQ_ENOTSUP;
     return solve<float>(nprob, probs, o, b, s, s, out, s, nullptr, CIQ_INVSQRT, infos, stream);
 }
 
@@ -1171,6 +1399,7 @@ int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double
         return CIQ_EINVAL;
     for (int q = 0; q < o->q; ++q)
         if (!(t[q] > 0.0) || !(w[q] > 0.0) || !std::isfinite(t[q]) || !std::isfinite(w[q])) return CIQ_EINVAL;
+    if (o->precond_rank != 0) return CIQ_ENOTSUP;
     if (o->dtype == CIQ_F64)
         return backward_impl<double>(p, o, mode, t, w, solves, g, s, ldg, db, lddb, dlengthscale, doutputscale,
                                      dnoise, info, stream);
@@ -1178,6 +1407,49 @@ int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double
         return backward_impl<float>(p, o, mode, t, w, solves, g, s, ldg, db, lddb, dlengthscale, doutputscale,
                                     dnoise, info, stream);
     return CIQ_ENOTSUP;
+}
+
+int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out, int* piv_out,
+                         double* trace_out, hipStream_t stream) {
+    if (!valid_problem(p) || !valid_dtype(dtype) || !l_out || !piv_out) return CIQ_EINVAL;
+    if (rank < 1 || rank > std::min(p->n, CIQ_MAX_RANK)) return CIQ_EINVAL;
+    const int n = p->n, dp = p->d;
+    double scale[CIQ_MAX_D], ones[CIQ_MAX_D];
+    point_scale(p, dtype, scale);
+    int ard = 0;
+    for (int k = 0; k < CIQ_MAX_D; ++k) {
+        ones[k] = 1.0;
+        if (k >= p->d) scale[k] = 0.0;
+        else if (scale[k] != scale[0]) ard = 1;
+    }
+    DevAlloc mem;
+    PcholScratch w{};
+    size_t off = 0;
+    double* xh = nullptr;
+    auto layout = [&](char* base) {
+        off = 0;
+        xh = carve<double>(base, off, (size_t)n * dp);
+        pchol_layout(n, rank, [&](size_t c) { return carve<double>(base, off, c); }, w);
+    };
+    layout(nullptr);
+    if (hipMalloc(&mem.p, off) != hipSuccess) {
+        (void)hipGetLastError();
+        mem.p = nullptr;
+        return CIQ_ENOMEM;
+    }
+    layout(static_cast<char*>(mem.p));
+    hipError_t e;
+    if (dtype == CIQ_F64)
+        e = launch_prep<double>(static_cast<const double*>(p->x), n, p->d, dp, ones, xh, stream);
+    else
+        e = launch_prep<float>(static_cast<const float*>(p->x), n, p->d, dp, ones, xh, stream);
+    if (e != hipSuccess) return CIQ_EHIP;
+    std::vector<int> piv;
+    double tr = 0.0;
+    STCHK(pchol_run(xh, n, dp, p->kernel, ard, scale, p->outputscale, rank, l_out, rank, w, piv, &tr, stream));
+    std::memcpy(piv_out, piv.data(), (size_t)rank * sizeof(int));
+    if (trace_out) *trace_out = tr;
+    return CIQ_OK;
 }
 
 }  // extern "C"

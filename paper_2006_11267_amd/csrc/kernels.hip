@@ -442,6 +442,8 @@ hipError_t launch_scalar(const Dev& d, hipStream_t st) {
 //   per unfrozen shift q: m_j = (q_j - delta m_{j-1} - eps m_{j-2}) * ginv,
 //                          acc += w_q tau m_j,  x^{(q)} += tau m_j  (if kept)
 //   if the column continues: q_{j+1} = (K q_j - beta_j q_{j-1} - alpha_j q_j) / beta_{j+1}
+// (preconditioned form, Appendix D: the recurrence consumes p_j = P^{-1} z_j
+// and the continuing column scales the finished w and P^{-1} w, see launch_update)
 // m_j overwrites m_{j-2}; q_{j+1} overwrites q_{j-1}.
 // Block: TS columns x RL row lanes; grid (blocks, ceil(s/TS), nprob).
 // ----------------------------------------------------------------------------
@@ -449,7 +451,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long long ysplit, int nsplit,
                                                      const T* qcur, T* qprev, const T* m_prev,
                                                      T* m_cur, T* acc, T* solves, long long mstride,
-                                                     int TS, float* q32) {
+                                                     int TS, float* q32, T* pnext) {
     extern __shared__ char smem[];
     if (!d.st->live) return;
     const int RL = 256 / TS;
@@ -502,6 +504,13 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
         }
         acc[idx] += a;
         if (flag == 2) {
+            if (pnext) {                        // preconditioned: y is w = z_{j+1} beta_{j+1}
+                qprev[idx] = y[idx] * ib;
+                const T pn = pnext[idx] * ib;
+                pnext[idx] = pn;
+                if (q32) q32[idx] = (float)pn;
+                continue;
+            }
             double ys = (double)y[idx];
             for (int k = 1; k < nsplit; ++k) ys += (double)y[k * ysplit + idx];
             const T vT = (T)ys - bj * qprev[idx];     // same arithmetic as the inner products
@@ -515,7 +524,8 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
 
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur, T* qprev,
-                         const T* m_prev, T* m_cur, T* acc, T* solves, float* q32, int max_n, hipStream_t st) {
+                         const T* m_prev, T* m_cur, T* acc, T* solves, float* q32, int max_n, hipStream_t st,
+                         T* pnext) {
     const size_t per = 5 * sizeof(T) + sizeof(int);   // LDS bytes per (shift, column)
     int TS = col_tile(d.s);
     while (TS > 1 && (size_t)d.Q * TS * per > 49152) TS >>= 1;   // coefficient tile <= 48 KB LDS
@@ -527,18 +537,19 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
     const size_t shm = (size_t)d.Q * TS * per;
     const long long mstride = (long long)d.rows_total * d.s;
     hipLaunchKernelGGL(update_kernel<T>, grid, dim3(256), shm, st, d, y, ysplit, nsplit, qcur, qprev,
-                       m_prev, m_cur, acc, solves, mstride, TS, q32);
+                       m_prev, m_cur, acc, solves, mstride, TS, q32, pnext);
     return hipGetLastError();
 }
 template hipError_t launch_update<double>(const Dev&, const double*, long long, int, const double*, double*,
-                                          const double*, double*, double*, double*, float*, int, hipStream_t);
+                                          const double*, double*, double*, double*, float*, int, hipStream_t,
+                                          double*);
 
 // ----------------------------------------------------------------------------
 // Start of a run: q_1 = b / ||b|| (0 for a zero column), q_0 = 0, acc = 0.
 // The caller has copied B into q and zeroed the direction/solve buffers.
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32) {
+__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32, T* pvec) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)d.rows_total * d.s;
     if (e >= total) return;
@@ -548,19 +559,27 @@ __global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32) {
     const T inv = (T)d.inv_beta_next[p * d.s + c];
     const T qv = q[e] * inv;
     q[e] = qv;
-    if (q32) q32[e] = (float)qv;
+    if (pvec) {
+        const T pv = pvec[e] * inv;
+        pvec[e] = pv;
+        if (q32) q32[e] = (float)pv;
+    } else if (q32) {
+        q32[e] = (float)qv;
+    }
     qprev[e] = (T)0;
     acc[e] = (T)0;
 }
 
 template <typename T>
-hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows, hipStream_t st) {
+hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows, hipStream_t st,
+                               T* pvec) {
     const long long total = (long long)rows * d.s;
     hipLaunchKernelGGL(init_vectors_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, d, q,
-                       qprev, acc, q32);
+                       qprev, acc, q32, pvec);
     return hipGetLastError();
 }
-template hipError_t launch_init_vectors<double>(const Dev&, double*, double*, double*, float*, int, hipStream_t);
+template hipError_t launch_init_vectors<double>(const Dev&, double*, double*, double*, float*, int, hipStream_t,
+                                                double*);
 
 // ----------------------------------------------------------------------------
 // Strided copy, fill, counter-based random start vector.

@@ -54,7 +54,7 @@ class Problem:
 
 
 def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, check_every=0, profile=False,
-          kernel_cache="auto", cache_budget_mib=0, graph=False):
+          kernel_cache="auto", cache_budget_mib=0, graph=False, precond_rank=0):
     o = L.ciq_opts()
     o.dtype = dtype_code
     o.q = int(q)
@@ -69,6 +69,7 @@ def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, ch
     o.kernel_cache = L.CACHE_MODES[kernel_cache]
     o.cache_budget_mib = int(cache_budget_mib)
     o.graph = 1 if graph else 0
+    o.precond_rank = int(precond_rank)
     return o
 
 
@@ -113,7 +114,7 @@ def ciq_eig_bounds(problem: Problem, steps: int = 20, v0: Optional[torch.Tensor]
 
 
 def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves, lanczos_steps, seed,
-           check_every, profile, kernel_cache, cache_budget_mib, graph):
+           check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank):
     lib = L.load()
     code = _dtype_code(problem.x, precision)
     b2 = b if b.dim() == 2 else b.reshape(-1, 1)
@@ -124,7 +125,7 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
     solves = torch.empty((n, q, s), dtype=_elem_dtype(code), device=b.device) if keep_solves else None
     p, keep = problem.c_struct()
     o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, kernel_cache,
-              cache_budget_mib, graph)
+              cache_budget_mib, graph, precond_rank)
     info = L.ciq_info()
     fn = getattr(lib, fn_name)
     L.check(fn(ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s, b2.stride(0),
@@ -138,19 +139,40 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
 def ciq_invsqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                     precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
                     lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
-                    kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False):
-    """K^{-1/2} B -> (out, info, solves or None)."""
+                    kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False,
+                    precond_rank: int = 0):
+    """K^{-1/2} B -> (out, info, solves or None). With precond_rank > 0 the
+    output is R' B, R' R'^T = K^{-1} (K^{-1/2} B up to a rotation)."""
     return _solve("ciq_invsqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank)
 
 
 def ciq_sqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                  precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
                  lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
-                 kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False):
-    """K^{1/2} B -> (out, info, solves or None)."""
+                 kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False,
+                 precond_rank: int = 0):
+    """K^{1/2} B -> (out, info, solves or None). With precond_rank > 0 the
+    output is R B, R R^T = K (K^{1/2} B up to a rotation)."""
     return _solve("ciq_sqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank)
+
+
+def ciq_pivoted_cholesky(problem: Problem, rank: int):
+    """Rank-`rank` partial pivoted Cholesky factor of outputscale * k(X, X):
+    (Lbar as an n x rank float64 device tensor, pivots (numpy, -1 after a
+    stop), trace of the residual)."""
+    lib = L.load()
+    n = problem.x.shape[0]
+    code = L.CIQ_F64 if problem.x.dtype == torch.float64 else L.CIQ_F32
+    lbar = torch.empty((n, int(rank)), dtype=torch.float64, device=problem.x.device)
+    piv = (ctypes.c_int * int(rank))()
+    tr = ctypes.c_double()
+    p, keep = problem.c_struct()
+    L.check(lib.ciq_pivoted_cholesky(ctypes.byref(p), code, int(rank), ctypes.c_void_p(lbar.data_ptr()), piv,
+                                     ctypes.byref(tr), _stream()), "ciq_pivoted_cholesky")
+    del keep
+    return lbar, np.array(piv[:], dtype=np.int64), tr.value
 
 
 def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tensor], q: int = 12,

@@ -134,7 +134,8 @@ def test_invalid_problem_rejected_before_device_work(lib, bad):
 
 
 @pytest.mark.parametrize("bad", [dict(q=0), dict(q=65), dict(max_iter=0), dict(tol=-1.0), dict(dtype=9),
-                                 dict(tol=float("nan")), dict(check_every=-1)])
+                                 dict(tol=float("nan")), dict(check_every=-1), dict(precond_rank=-1),
+                                 dict(precond_rank=1025)])
 def test_invalid_options_rejected(lib, bad):
     p, keep = _bad_problem()
     o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4)
@@ -164,6 +165,35 @@ def test_invalid_sizes_rejected(lib):
     infos = (L.ciq_info * 1)()
     assert lib.ciq_invsqrt_mvm_batched(0, probs, ctypes.byref(o), bp, 2, bp, infos, None) == L.CIQ_EINVAL
     del keep
+
+
+def test_preconditioner_arguments_rejected(lib):
+    """Preconditioning needs sigma^2 > 0; the batched call and the backward do
+    not take it; the factor entry validates rank and pointers. All checked
+    before any device work."""
+    fake = ctypes.c_void_p(512)
+    info = L.ciq_info()
+    p0, keep0 = _bad_problem(noise=0.0)
+    o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4, precond_rank=4)
+    assert lib.ciq_sqrt_mvm(ctypes.byref(p0), ctypes.byref(o), fake, 2, 2, fake, 2, None, ctypes.byref(info),
+                            None) == L.CIQ_EINVAL
+    p, keep = _bad_problem()
+    probs = (L.ciq_problem * 1)(p)
+    bp = (ctypes.c_void_p * 1)(512)
+    infos = (L.ciq_info * 1)()
+    assert lib.ciq_invsqrt_mvm_batched(1, probs, ctypes.byref(o), bp, 2, bp, infos, None) == L.CIQ_ENOTSUP
+    t = (ctypes.c_double * 8)(*([1.0] * 8))
+    assert lib.ciq_backward(ctypes.byref(p), ctypes.byref(o), L.CIQ_INVSQRT, t, t, fake, fake, 2, 2, None, 2,
+                            None, None, None, ctypes.byref(info), None) == L.CIQ_ENOTSUP
+    piv = (ctypes.c_int * 20)()
+    tr = ctypes.c_double()
+    for rank in (0, 11, 1025):
+        assert lib.ciq_pivoted_cholesky(ctypes.byref(p), L.CIQ_F32, rank, fake, piv, ctypes.byref(tr), None) \
+            == L.CIQ_EINVAL
+    assert lib.ciq_pivoted_cholesky(ctypes.byref(p), L.CIQ_F32, 4, None, piv, None, None) == L.CIQ_EINVAL
+    assert lib.ciq_pivoted_cholesky(ctypes.byref(p), L.CIQ_F32, 4, fake, None, None, None) == L.CIQ_EINVAL
+    assert lib.ciq_pivoted_cholesky(ctypes.byref(p), 9, 4, fake, piv, None, None) == L.CIQ_EINVAL
+    del keep, keep0
 
 
 def test_strerror(lib):
