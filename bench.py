@@ -192,6 +192,9 @@ def main() -> int:
                     help="2: the metric's workload (default). 3: RBF-ARD N=100,000 d=8 S=256 per precision form; "
                          "4: 64 batched problems; 5: SVGP whitening forward + backward at M=5,000 "
                          "(secondary measurements, one JSON line each)")
+    ap.add_argument("--precond-rank", type=int, default=0,
+                    help="R > 0: pivoted-Cholesky preconditioned CIQ of rank R (the output is R B with R R^T = K, "
+                         "K^{1/2} B up to a rotation; secondary measurement)")
     ap.add_argument("--precision", choices=["f64", "f32", "bf16x3", "f16x3"], default="f32",
                     help="f32: FP32 MFMA products of FP64 entries rounded once (resident K), FP64 vectors; "
                          "f64: FP64 throughout; bf16x3 / f16x3: split-operand half-precision products")
@@ -221,7 +224,7 @@ def main() -> int:
 
     def step(profile=False):
         return ciq.ciq_sqrt_mvm(prob, b, q=q, max_iter=args.max_iter, tol=tol, seed=4001, profile=profile,
-                                kernel_cache=args.kernel_cache, precision=prec)
+                                kernel_cache=args.kernel_cache, precision=prec, precond_rank=args.precond_rank)
 
     if args.counters:
         src = torch.empty(64 << 20, dtype=torch.float64, device=dev).normal_()
@@ -229,7 +232,8 @@ def main() -> int:
         dst.copy_(src)                       # reference copy: 512 MiB read + 512 MiB written
         torch.cuda.synchronize()
         out, info, _ = ciq.ciq_sqrt_mvm(prob, b, q=q, max_iter=4, tol=tol, seed=4001,
-                                        kernel_cache=args.kernel_cache, precision=prec)
+                                        kernel_cache=args.kernel_cache, precision=prec,
+                                        precond_rank=args.precond_rank)
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "copy_bytes": src.numel() * 8, "iters": info["iters"],
                           "mvm_count": info["mvm_count"]}), flush=True)
@@ -258,12 +262,15 @@ def main() -> int:
 
     accuracy = None
     if args.check_cols > 0:
-        # reference: the FP64 path on the same (rounded) inputs, same bounds, tol 1e-10
+        # reference: the FP64 path on the same (rounded) inputs, same bounds,
+        # tol 1e-10 (preconditioned: the same rank, hence the same factor of
+        # the same FP64 points, so the same rotation)
         k = min(args.check_cols, s)
         bk = b[:, :k].double().contiguous()
         p64 = ciq.Problem(x.double().contiguous(), p.kernel, p.lengthscale, p.outputscale, p.noise)
         ref, rinfo, _ = ciq.ciq_sqrt_mvm(p64, bk, q=q, max_iter=20000, tol=1e-10, seed=4001,
-                                         bounds=(info["lambda_min"], info["lambda_max"]))
+                                         bounds=(info["lambda_min"], info["lambda_max"]),
+                                         precond_rank=args.precond_rank)
         torch.cuda.synchronize()
         o = out[:, :k].double().cpu().numpy()
         r = ref.double().cpu().numpy()
@@ -301,6 +308,9 @@ def main() -> int:
             "max_rel_residual": info["max_rel_residual"], "lambda_min": info["lambda_min"],
             "lambda_max": info["lambda_max"], "mvm_per_step": info["mvm_count"],
             "kernel_cached": info["kernel_cached"], "accuracy": accuracy,
+            "precond_rank": args.precond_rank,
+            **({"precond_pivots": info["precond_rank"], "precond_trace": info["precond_trace"],
+                "output": "R B with R R^T = K (K^{1/2} B up to a rotation)"} if args.precond_rank else {}),
         },
         "roofline": {
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

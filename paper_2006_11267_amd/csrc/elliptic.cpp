@@ -80,9 +80,10 @@ int hht_quadrature(double lmin, double lmax, int Q, double* t, double* w) {
 
 // Eigenvalues/vectors of a small symmetric matrix (row-major n x n) by cyclic
 // Jacobi rotations (Golub & Van Loan 8.5). Eigenvector j is column j of v.
+// The eigenvectors are accumulated as rows of V^T (contiguous updates).
 void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& evals, std::vector<double>& v) {
-    v.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    std::vector<double> vt((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) vt[(size_t)i * n + i] = 1.0;
     double norm = 0.0;
     for (double x : a) norm += x * x;
     for (int sweep = 0; sweep < 100; ++sweep) {
@@ -103,21 +104,28 @@ void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& evals, s
                     a[(size_t)k * n + p] = c * akp - s * akq;
                     a[(size_t)k * n + q] = s * akp + c * akq;
                 }
+                double* ap = &a[(size_t)p * n];
+                double* aq = &a[(size_t)q * n];
                 for (int k = 0; k < n; ++k) {
-                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
-                    a[(size_t)p * n + k] = c * apk - s * aqk;
-                    a[(size_t)q * n + k] = s * apk + c * aqk;
+                    const double apk = ap[k], aqk = aq[k];
+                    ap[k] = c * apk - s * aqk;
+                    aq[k] = s * apk + c * aqk;
                 }
+                double* vp = &vt[(size_t)p * n];
+                double* vq = &vt[(size_t)q * n];
                 for (int k = 0; k < n; ++k) {
-                    const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
-                    v[(size_t)k * n + p] = c * vkp - s * vkq;
-                    v[(size_t)k * n + q] = s * vkp + c * vkq;
+                    const double x = vp[k], y = vq[k];
+                    vp[k] = c * x - s * y;
+                    vq[k] = s * x + c * y;
                 }
             }
         }
     }
     evals.resize(n);
     for (int i = 0; i < n; ++i) evals[i] = a[(size_t)i * n + i];
+    v.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) v[(size_t)k * n + j] = vt[(size_t)j * n + k];
 }
 
 // Widened bounds from a Lanczos tridiagonal (alpha[0..J), beta[0..J), beta[J-1]

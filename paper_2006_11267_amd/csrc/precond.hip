@@ -8,9 +8,10 @@
 //     P^{-1} x  : alpha0 = 1/sigma^2, f = -1 / (sigma^2 (lam + sigma^2))
 //     P^{1/2} x : alpha0 = sigma,     f = 1 / (sqrt(lam + sigma^2) + sigma)
 // (matrix inversion lemma and the exact square root of a low-rank-plus-
-// diagonal matrix, written without cancellation). Everything here is FP64
-// VALU work of O(n R s) per application, small next to the O(n^2 s) kernel
-// product it accompanies; the factorisation is O(n R^2) once per call.
+// diagonal matrix, written without cancellation). Everything here is FP64:
+// the two contractions of an application (U^T x, then U T) on FP64 MFMA,
+// O(n R s) per application, small next to the O(n^2 s) kernel product it
+// accompanies; the factorisation is O(n R^2) VALU work once per call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -163,73 +164,84 @@ __global__ __launch_bounds__(256) void pchol_col_kernel(PcholArgs a, int m) {
 }
 
 // ---- low-rank products -------------------------------------------------------
-// Tile 32 r x 64 s per block, 32-row slabs of A and X staged in LDS; thread
-// (tr, tc) accumulates r = r0 + 2 tr + {0,1}, s = s0 + tc + 16 k, k = 0..3.
+// Both are dense FP64 contractions and run on v_mfma_f64_16x16x4_f64: lane l
+// supplies A-operand element [l%16][l/16] and B-operand element [l/16][l%16];
+// the accumulator holds D[l/16 + 4v][l%16] in register v.
+typedef double pdx4 __attribute__((ext_vector_type(4)));
+
+// part: the block owns 64 r x 64 s of one row chunk; wave w the r-tile
+// r0 + 16 w against four 16-column s-tiles. MFMA (i, k, j) = (r, row, s):
+// A-operand A[row][r] (16 consecutive r per row), B-operand X[row][s].
 __global__ __launch_bounds__(256) void lr_part_kernel(const double* __restrict__ A, int lda,
                                                       const double* __restrict__ X, int ldx, int n, int R, int S,
                                                       int rows_per_chunk, double* __restrict__ part,
                                                       const int* done) {
     if (done != nullptr && *done) return;
-    __shared__ double As[32][33];
-    __shared__ double Xs[32][64];
-    const int chunk = blockIdx.x, r0 = blockIdx.y * 32, c0 = blockIdx.z * 64;
+    const int chunk = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int r0 = blockIdx.y * 64 + wave * 16, s0 = blockIdx.z * 64;
     const int i0 = chunk * rows_per_chunk;
     const int i1 = min(n, i0 + rows_per_chunk);
-    const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
-    double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-    for (int ib = i0; ib < i1; ib += 32) {
-        __syncthreads();
+    const int ra = r0 + lr;
+    const bool ra_ok = ra < R;
+    pdx4 acc[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = t + 256 * k, row = e >> 5, rr = e & 31;
-            const int i = ib + row, r = r0 + rr;
-            As[row][rr] = (i < i1 && r < R) ? A[(long long)i * lda + r] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = t + 256 * k, row = e >> 6, cc = e & 63;
-            const int i = ib + row, c = c0 + cc;
-            Xs[row][cc] = (i < i1 && c < S) ? X[(long long)i * ldx + c] : 0.0;
-        }
-        __syncthreads();
+    for (int sb = 0; sb < 4; ++sb) acc[sb] = pdx4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int row = 0; row < 32; ++row) {
-            const double a0 = As[row][2 * tr], a1 = As[row][2 * tr + 1];
+    for (int ib = i0; ib < i1; ib += 4) {
+        const int i = ib + lk;
+        const bool iok = i < i1;
+        const double a = (iok && ra_ok) ? A[(long long)i * lda + ra] : 0.0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double x = Xs[row][tc + 16 * k];
-                acc[0][k] = fma(a0, x, acc[0][k]);
-                acc[1][k] = fma(a1, x, acc[1][k]);
-            }
+        for (int sb = 0; sb < 4; ++sb) {
+            const int sc = s0 + sb * 16 + lr;
+            const double x = (iok && sc < S) ? X[(long long)i * ldx + sc] : 0.0;
+            acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x, acc[sb], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int r = r0 + 2 * tr + u;
-        if (r >= R) continue;
+    for (int sb = 0; sb < 4; ++sb) {
+        const int sc = s0 + sb * 16 + lr;
+        if (sc >= S) continue;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int c = c0 + tc + 16 * k;
-            if (c < S) part[((long long)chunk * R + r) * S + c] = acc[u][k];
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + lk + 4 * v;
+            if (r < R) part[((long long)chunk * R + r) * S + sc] = acc[sb][v];
         }
     }
 }
 
-__global__ void lr_reduce_kernel(const double* __restrict__ part, int nchunk, int R, int S,
-                                 const double* __restrict__ f, double* __restrict__ T, int ldt, const int* done) {
+// T[r][c] = f_r sum_ch part[ch][r][c]: 16 elements x 16 lanes per block; lane
+// g sums chunks g, g + 16, ... (independent loads in flight), then the 16
+// lane sums are added in lane order (deterministic).
+__global__ __launch_bounds__(256) void lr_reduce_kernel(const double* __restrict__ part, int nchunk, int R, int S,
+                                                        const double* __restrict__ f, double* __restrict__ T, int ldt,
+                                                        const int* done) {
     if (done != nullptr && *done) return;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[16][17];
+    const int el = threadIdx.x & 15, g = threadIdx.x >> 4;
     const long long total = (long long)R * S;
-    if (e >= total) return;
-    const int r = (int)(e / S), c = (int)(e - (long long)r * S);
-    double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[(long long)ch * total + e];
-    if (f != nullptr) s *= f[r];
-    T[(long long)r * ldt + c] = s;
+    const long long e = (long long)blockIdx.x * 16 + el;
+    double acc = 0.0;
+    if (e < total) {
+#pragma unroll 4
+        for (int ch = g; ch < nchunk; ch += 16) acc += part[(long long)ch * total + e];
+    }
+    red[g][el] = acc;
+    __syncthreads();
+    if (threadIdx.x < 16 && e < total) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sum += red[k][el];
+        const int r = (int)(e / S), c = (int)(e - (long long)r * S);
+        if (f != nullptr) sum *= f[r];
+        T[(long long)r * ldt + c] = sum;
+    }
 }
 
-// Tile 64 rows x 64 s per block, r in slabs of 32 through LDS; thread (tr, tc)
-// owns rows i0 + tr + 16 u and columns s0 + tc + 16 k (u, k = 0..3).
+// apply: the block owns 64 rows x 64 s; wave w rows i0 + 16 w against four
+// s-tiles; r runs in slabs of 32 staged in LDS. MFMA (i, k, j) = (row, r, s):
+// A-operand A[row][r], B-operand T[r][s].
 __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const double* X, int ldx,
                                                        const double* __restrict__ A, int lda,
                                                        const double* __restrict__ T, int ldt, int n, int R, int S,
@@ -237,79 +249,86 @@ __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const doub
                                                        const int* __restrict__ colmask, const int* done) {
     if (done != nullptr && *done) return;
     __shared__ double As[64][33];
-    __shared__ double Ts[32][64];
+    __shared__ double Ts[32][80];
     __shared__ double red[16][64];
-    const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-    const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
-    double acc[4][4];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int i0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
+    pdx4 acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[u][k] = 0.0;
-    for (int r0 = 0; r0 < R; r0 += 32) {
+    for (int sb = 0; sb < 4; ++sb) acc[sb] = pdx4{0.0, 0.0, 0.0, 0.0};
+    for (int rb = 0; rb < R; rb += 32) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int e = t + 256 * k, row = e >> 5, rr = e & 31;
-            const int i = i0 + row, r = r0 + rr;
+            const int e = tid + 256 * k, row = e >> 5, rr = e & 31;
+            const int i = i0 + row, r = rb + rr;
             As[row][rr] = (i < n && r < R) ? A[(long long)i * lda + r] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int e = t + 256 * k, rr = e >> 6, cc = e & 63;
-            const int r = r0 + rr, c = c0 + cc;
+            const int e = tid + 256 * k, rr = e >> 6, cc = e & 63;
+            const int r = rb + rr, c = s0 + cc;
             Ts[rr][cc] = (r < R && c < S) ? T[(long long)r * ldt + c] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < 32; ++rr) {
-            double av[4], tv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[tr + 16 * u][rr];
+        for (int kk = 0; kk < 32; kk += 4) {
+            const double a = As[wave * 16 + lr][kk + lk];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) tv[k] = Ts[rr][tc + 16 * k];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc[u][k] = fma(av[u], tv[k], acc[u][k]);
+            for (int sb = 0; sb < 4; ++sb)
+                acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[kk + lk][sb * 16 + lr], acc[sb], 0, 0, 0);
         }
     }
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = c0 + tc + 16 * k;
+    for (int sb = 0; sb < 4; ++sb) {
+        const int c = s0 + sb * 16 + lr;
         if (c >= S) continue;
         if (colmask != nullptr && colmask[c] == 0) continue;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + tr + 16 * u;
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wave * 16 + lk + 4 * v;
             if (i >= n) continue;
             const double x = (X != nullptr) ? X[(long long)i * ldx + c] : 0.0;
-            const double y = alpha0 * x + acc[u][k];
+            const double y = alpha0 * x + acc[sb][v];
             Y[(long long)i * ldy + c] = y;
-            dsum[k] = fma(x, y, dsum[k]);
+            dsum[sb] = fma(x, y, dsum[sb]);
         }
     }
     if (dotp == nullptr) return;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) red[tr][tc + 16 * k] = dsum[k];
+    for (int sb = 0; sb < 4; ++sb) red[wave * 4 + lk][sb * 16 + lr] = dsum[sb];
     __syncthreads();
-    if (t < 64 && c0 + t < S) {
-        double s = 0.0;
+    if (tid < 64 && s0 + tid < S) {
+        double sum = 0.0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) s += red[r][t];
-        dotp[(long long)blockIdx.x * S + c0 + t] = s;
+        for (int g = 0; g < 16; ++g) sum += red[g][tid];
+        dotp[(long long)blockIdx.x * S + s0 + tid] = sum;
     }
 }
 
-__global__ void lr_dotsum_kernel(const double* __restrict__ dotp, int nblk, int S, double* __restrict__ out,
-                                 const int* done) {
+// out[c] = sum_b dotp[b][c]: 64 columns x 16 lanes per block, lane g sums
+// blocks g, g + 16, ..., then the lane sums in lane order.
+__global__ __launch_bounds__(1024) void lr_dotsum_kernel(const double* __restrict__ dotp, int nblk, int S,
+                                                         double* __restrict__ out, const int* done) {
     if (done != nullptr && *done) return;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= S) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += dotp[(long long)b * S + c];
-    out[c] = s;
+    __shared__ double red[16][64];
+    const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    double acc = 0.0;
+    if (c < S) {
+#pragma unroll 4
+        for (int b = g; b < nblk; b += 16) acc += dotp[(long long)b * S + c];
+    }
+    red[g][cl] = acc;
+    __syncthreads();
+    if (g == 0 && c < S) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sum += red[k][cl];
+        out[c] = sum;
+    }
 }
 
 // Single-problem runs only (the preconditioned path is not batched).
@@ -352,7 +371,7 @@ hipError_t launch_pchol_col(const PcholArgs& a, int m, hipStream_t st) {
 }
 
 int lr_part_chunks(int n, int R, int S) {
-    const int tiles = ((R + 31) / 32) * ((S + 63) / 64);
+    const int tiles = ((R + 63) / 64) * ((S + 63) / 64);
     int nchunk = (1024 + tiles - 1) / tiles;
     nchunk = std::min(nchunk, (n + 63) / 64);
     return std::max(nchunk, 1);
@@ -361,7 +380,7 @@ int lr_part_chunks(int n, int R, int S) {
 hipError_t launch_lr_part(const double* A, int lda, const double* X, int ldx, int n, int R, int S, int nchunk,
                           double* part, const int* done, hipStream_t st) {
     const int rows_per_chunk = (n + nchunk - 1) / nchunk;
-    dim3 grid(nchunk, (R + 31) / 32, (S + 63) / 64);
+    dim3 grid(nchunk, (R + 63) / 64, (S + 63) / 64);
     hipLaunchKernelGGL(lr_part_kernel, grid, dim3(256), 0, st, A, lda, X, ldx, n, R, S, rows_per_chunk, part,
                        done);
     return hipGetLastError();
@@ -370,7 +389,7 @@ hipError_t launch_lr_part(const double* A, int lda, const double* X, int ldx, in
 hipError_t launch_lr_reduce(const double* part, int nchunk, int R, int S, const double* f, double* T, int ldt,
                             const int* done, hipStream_t st) {
     const long long total = (long long)R * S;
-    hipLaunchKernelGGL(lr_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, nchunk, R,
+    hipLaunchKernelGGL(lr_reduce_kernel, dim3((unsigned)((total + 15) / 16)), dim3(256), 0, st, part, nchunk, R,
                        S, f, T, ldt, done);
     return hipGetLastError();
 }
@@ -387,7 +406,7 @@ hipError_t launch_lr_apply(double alpha0, const double* X, int ldx, const double
 }
 
 hipError_t launch_lr_dotsum(const double* dotp, int nblk, int S, double* out, const int* done, hipStream_t st) {
-    hipLaunchKernelGGL(lr_dotsum_kernel, dim3((S + 63) / 64), dim3(64), 0, st, dotp, nblk, S, out, done);
+    hipLaunchKernelGGL(lr_dotsum_kernel, dim3((S + 63) / 64), dim3(1024), 0, st, dotp, nblk, S, out, done);
     return hipGetLastError();
 }
 

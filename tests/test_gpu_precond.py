@@ -96,7 +96,8 @@ def test_precond_small_j_parity_fp64(mode, J, cache):
     bounds on both sides: GPU and oracle agree to rounding (the factors,
     the Gram eigendecompositions and the products round differently). The
     bar is 10x the oracle's own move under one-ulp perturbations of the
-    entries of K and of the Gram matrix behind P (see _Rounded)."""
+    entries of K and of the Gram matrix behind P (see _Rounded), and at
+    least eps kappa(P) (the rounding scale of any evaluation of P^{-1} x)."""
     torch = torch_cuda()
     ciq = ciq_module()
     kind, n, d, s, rank, noise = "matern52", 2100, 4, 33, 100, 1e-3
@@ -126,7 +127,12 @@ def test_precond_small_j_parity_fp64(mode, J, cache):
                                         mode, return_solves=True)
         spread = max(spread, colwise_rel(alt, ref).max())
         spread_x = max(spread_x, max(colwise_rel(altX[qi], X[qi]).max() for qi in range(10)))
-    bar, bar_x = max(10.0 * spread, 1e-11), max(10.0 * spread_x, 1e-11)
+    # floor: P^{-1} x is x / sigma^2 minus a low-rank correction, so any FP64
+    # evaluation carries absolute errors ~eps |x| / sigma^2, i.e. relative
+    # eps kappa(P) along the leading eigenvectors of P
+    kappa_p = (pre.lam.max() + noise) / noise
+    floor = max(2.2e-16 * kappa_p, 1e-11)
+    bar, bar_x = max(10.0 * spread, floor), max(10.0 * spread_x, floor)
     gap = colwise_rel(out.cpu().numpy(), ref).max()
     sv = solves.cpu().numpy()
     gap_x = max(colwise_rel(sv[:, qi, :], X[qi]).max() for qi in range(10))
