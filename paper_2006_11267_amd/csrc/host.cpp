@@ -23,7 +23,7 @@ namespace ciq {
 int hht_quadrature(double lmin, double lmax, int Q, double* t, double* w);
 void bounds_from_tridiag(int J, const double* alpha, const double* beta, double noise, double* lmin,
                          double* lmax);
-void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& evals, std::vector<double>& v);
+void sym_eig_tridiag(int n, std::vector<double>& a, std::vector<double>& evals, std::vector<double>& v);
 }  // namespace ciq
 
 using namespace ciq;
@@ -274,8 +274,8 @@ int pc_apply(const Precond& pc, double alpha0, const double* f, const double* X,
     return CIQ_OK;
 }
 
-// Factorisation, Gram matrix, its eigendecomposition (host, cyclic Jacobi)
-// and U = Lbar V for one problem whose FP64 points are xh (n x dp).
+// Factorisation, Gram matrix, its eigendecomposition (host, Householder +
+// implicit QR) and U = Lbar V for one problem whose FP64 points are xh (n x dp).
 int pc_build(const ciq_problem& p, const double* xh, int dp, int kernel, int ard, const double* scale, int rank,
              int s_cap, Precond& pc, hipStream_t st) {
     const int n = p.n;
@@ -322,7 +322,7 @@ int pc_build(const ciq_problem& p, const double* xh, int dp, int kernel, int ard
             const double m = 0.5 * (G[(size_t)i * R + j] + G[(size_t)j * R + i]);
             G[(size_t)i * R + j] = G[(size_t)j * R + i] = m;
         }
-    sym_eig_jacobi(R, G, lam, V);
+    sym_eig_tridiag(R, G, lam, V);
     std::vector<double> fin(R), fsq(R);
     const double s2 = p.noise, sg = std::sqrt(p.noise);
     for (int r = 0; r < R; ++r) {
