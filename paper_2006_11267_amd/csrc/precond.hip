@@ -169,9 +169,12 @@ __global__ __launch_bounds__(256) void pchol_col_kernel(PcholArgs a, int m) {
 // the accumulator holds D[l/16 + 4v][l%16] in register v.
 typedef double pdx4 __attribute__((ext_vector_type(4)));
 
-// part: the block owns 64 r x 64 s of one row chunk; wave w the r-tile
-// r0 + 16 w against four 16-column s-tiles. MFMA (i, k, j) = (r, row, s):
-// A-operand A[row][r] (16 consecutive r per row), B-operand X[row][s].
+// part: the block owns 128 r x 64 s of one row chunk; wave w the r-tiles
+// r0 + 32 w + {0, 16} against four 16-column s-tiles (8 accumulators).
+// MFMA (i, k, j) = (r, row, s): A-operand A[row][r] (16 consecutive r per
+// row), B-operand X[row][s]. Operands of the next group of four k-steps are
+// loaded into registers while the current group's 32 MFMAs run.
+constexpr int kPartGroup = 4;
 __global__ __launch_bounds__(256) void lr_part_kernel(const double* __restrict__ A, int lda,
                                                       const double* __restrict__ X, int ldx, int n, int R, int S,
                                                       int rows_per_chunk, double* __restrict__ part,
@@ -179,36 +182,63 @@ __global__ __launch_bounds__(256) void lr_part_kernel(const double* __restrict__
     if (done != nullptr && *done) return;
     const int chunk = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-    const int r0 = blockIdx.y * 64 + wave * 16, s0 = blockIdx.z * 64;
+    const int r0 = blockIdx.y * 128 + wave * 32, s0 = blockIdx.z * 64;
     const int i0 = chunk * rows_per_chunk;
     const int i1 = min(n, i0 + rows_per_chunk);
-    const int ra = r0 + lr;
-    const bool ra_ok = ra < R;
-    pdx4 acc[4];
+    const bool ra_ok[2] = {r0 + lr < R, r0 + 16 + lr < R};
+    bool sc_ok[4];
 #pragma unroll
-    for (int sb = 0; sb < 4; ++sb) acc[sb] = pdx4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int ib = i0; ib < i1; ib += 4) {
-        const int i = ib + lk;
-        const bool iok = i < i1;
-        const double a = (iok && ra_ok) ? A[(long long)i * lda + ra] : 0.0;
+    for (int sb = 0; sb < 4; ++sb) sc_ok[sb] = s0 + sb * 16 + lr < S;
+    pdx4 acc[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) acc[t][sb] = pdx4{0.0, 0.0, 0.0, 0.0};
+    double ga[kPartGroup][2], gx[kPartGroup][4];
+    auto load = [&](int ib) {
+#pragma unroll
+        for (int g = 0; g < kPartGroup; ++g) {
+            const int i = ib + 4 * g + lk;
+            const bool iok = i < i1;
+            const double* ar = A + (long long)i * lda + r0 + lr;
+            const double* xr = X + (long long)i * ldx + s0 + lr;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) ga[g][t] = (iok && ra_ok[t]) ? ar[16 * t] : 0.0;
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb) gx[g][sb] = (iok && sc_ok[sb]) ? xr[16 * sb] : 0.0;
+        }
+    };
+    if (i0 < i1) load(i0);
+    for (int ib = i0; ib < i1; ib += 4 * kPartGroup) {
+        double ca[kPartGroup][2], cx[kPartGroup][4];
+#pragma unroll
+        for (int g = 0; g < kPartGroup; ++g) {
+            ca[g][0] = ga[g][0];
+            ca[g][1] = ga[g][1];
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb) cx[g][sb] = gx[g][sb];
+        }
+        if (ib + 4 * kPartGroup < i1) load(ib + 4 * kPartGroup);
+#pragma unroll
+        for (int g = 0; g < kPartGroup; ++g)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int sb = 0; sb < 4; ++sb)
+                    acc[t][sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[g][t], cx[g][sb], acc[t][sb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
             const int sc = s0 + sb * 16 + lr;
-            const double x = (iok && sc < S) ? X[(long long)i * ldx + sc] : 0.0;
-            acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x, acc[sb], 0, 0, 0);
-        }
-    }
+            if (sc >= S) continue;
 #pragma unroll
-    for (int sb = 0; sb < 4; ++sb) {
-        const int sc = s0 + sb * 16 + lr;
-        if (sc >= S) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + lk + 4 * v;
-            if (r < R) part[((long long)chunk * R + r) * S + sc] = acc[sb][v];
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 16 * t + lk + 4 * v;
+                if (r < R) part[((long long)chunk * R + r) * S + sc] = acc[t][sb][v];
+            }
         }
-    }
 }
 
 // T[r][c] = f_r sum_ch part[ch][r][c]: 16 elements x 16 lanes per block; lane
@@ -240,45 +270,56 @@ __global__ __launch_bounds__(256) void lr_reduce_kernel(const double* __restrict
 }
 
 // apply: the block owns 64 rows x 64 s; wave w rows i0 + 16 w against four
-// s-tiles; r runs in slabs of 32 staged in LDS. MFMA (i, k, j) = (row, r, s):
-// A-operand A[row][r], B-operand T[r][s].
+// s-tiles. MFMA (i, k, j) = (row, r, s): A-operand A[row][r] (each lane walks
+// its row 4 r at a time), B-operand T[r][s] (small, L2-resident). Operands of
+// the next group of four k-steps are loaded while the current group runs.
+constexpr int kApplyGroup = 4;
 __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const double* X, int ldx,
                                                        const double* __restrict__ A, int lda,
                                                        const double* __restrict__ T, int ldt, int n, int R, int S,
                                                        double* Y, int ldy, double* __restrict__ dotp,
                                                        const int* __restrict__ colmask, const int* done) {
     if (done != nullptr && *done) return;
-    __shared__ double As[64][33];
-    __shared__ double Ts[32][80];
     __shared__ double red[16][64];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int i0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
+    const int ia = i0 + wave * 16 + lr;           // this lane's A-operand row
+    const bool ia_ok = ia < n;
+    const double* arow = A + (long long)(ia_ok ? ia : 0) * lda;
+    bool sc_ok[4];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) sc_ok[sb] = s0 + sb * 16 + lr < S;
     pdx4 acc[4];
 #pragma unroll
     for (int sb = 0; sb < 4; ++sb) acc[sb] = pdx4{0.0, 0.0, 0.0, 0.0};
-    for (int rb = 0; rb < R; rb += 32) {
-        __syncthreads();
+    double ga[kApplyGroup], gt[kApplyGroup][4];
+    auto load = [&](int rb) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = tid + 256 * k, row = e >> 5, rr = e & 31;
-            const int i = i0 + row, r = rb + rr;
-            As[row][rr] = (i < n && r < R) ? A[(long long)i * lda + r] : 0.0;
+        for (int g = 0; g < kApplyGroup; ++g) {
+            const int r = rb + 4 * g + lk;
+            const bool rok = r < R;
+            ga[g] = (ia_ok && rok) ? arow[r] : 0.0;
+            const double* tr = T + (long long)r * ldt + s0 + lr;
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb) gt[g][sb] = (rok && sc_ok[sb]) ? tr[16 * sb] : 0.0;
         }
+    };
+    load(0);
+    for (int rb = 0; rb < R; rb += 4 * kApplyGroup) {
+        double ca[kApplyGroup], ct[kApplyGroup][4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = tid + 256 * k, rr = e >> 6, cc = e & 63;
-            const int r = rb + rr, c = s0 + cc;
-            Ts[rr][cc] = (r < R && c < S) ? T[(long long)r * ldt + c] : 0.0;
+        for (int g = 0; g < kApplyGroup; ++g) {
+            ca[g] = ga[g];
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb) ct[g][sb] = gt[g][sb];
         }
-        __syncthreads();
+        if (rb + 4 * kApplyGroup < R) load(rb + 4 * kApplyGroup);
 #pragma unroll
-        for (int kk = 0; kk < 32; kk += 4) {
-            const double a = As[wave * 16 + lr][kk + lk];
+        for (int g = 0; g < kApplyGroup; ++g)
 #pragma unroll
             for (int sb = 0; sb < 4; ++sb)
-                acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[kk + lk][sb * 16 + lr], acc[sb], 0, 0, 0);
-        }
+                acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[g], ct[g][sb], acc[sb], 0, 0, 0);
     }
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -371,7 +412,7 @@ hipError_t launch_pchol_col(const PcholArgs& a, int m, hipStream_t st) {
 }
 
 int lr_part_chunks(int n, int R, int S) {
-    const int tiles = ((R + 63) / 64) * ((S + 63) / 64);
+    const int tiles = ((R + 127) / 128) * ((S + 63) / 64);
     int nchunk = (1024 + tiles - 1) / tiles;
     nchunk = std::min(nchunk, (n + 63) / 64);
     return std::max(nchunk, 1);
@@ -380,7 +421,7 @@ int lr_part_chunks(int n, int R, int S) {
 hipError_t launch_lr_part(const double* A, int lda, const double* X, int ldx, int n, int R, int S, int nchunk,
                           double* part, const int* done, hipStream_t st) {
     const int rows_per_chunk = (n + nchunk - 1) / nchunk;
-    dim3 grid(nchunk, (R + 63) / 64, (S + 63) / 64);
+    dim3 grid(nchunk, (R + 127) / 128, (S + 63) / 64);
     hipLaunchKernelGGL(lr_part_kernel, grid, dim3(256), 0, st, A, lda, X, ldx, n, R, S, rows_per_chunk, part,
                        done);
     return hipGetLastError();
