@@ -234,3 +234,37 @@ def test_precond_zero_and_ragged_columns():
     for c in (0, 4):
         one, _, _ = ciq.ciq_sqrt_mvm(prob, torch.from_numpy(np.ascontiguousarray(b[:, c:c + 1])).cuda(), **kw)
         assert colwise_rel(o[:, c:c + 1], one.cpu().numpy()).max() < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3", "f32"])
+def test_precond_other_products_and_rank_clamp(prec):
+    """The preconditioned step is independent of the product's precision form:
+    split BF16/FP16 products and the on-the-fly FP32 product (cache off) give
+    results satisfying A^T K A = B^T B to their product accuracy; a rank above
+    n is clamped to n (the factor then stops at the numerical rank)."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    x, b, ls = _inputs(1800, 5, 8, 31, np.float32)
+    announce(f"precond product form {prec}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), "matern52", ls, 1.0, 1e-2)
+    bt = torch.from_numpy(b).cuda()
+    a, info, _ = ciq.ciq_invsqrt_mvm(prob, bt, q=12, max_iter=2000, tol=1e-7, precond_rank=60,
+                                     precision=prec, kernel_cache="off")
+    assert info["converged"] and info["precond_rank"] == 60
+    p64 = ciq.Problem(prob.x.double().contiguous(), "matern52", ls, 1.0, 1e-2)
+    ka = ciq.ciq_kernel_mvm(p64, a.double().contiguous())
+    torch.cuda.synchronize()
+    A, KA = a.double().cpu().numpy(), ka.cpu().numpy()
+    BtB = b.astype(np.float64).T @ b.astype(np.float64)
+    err = np.abs(A.T @ KA - BtB).max() / np.abs(BtB).max()
+    print(f"{prec}: identity error {err:.2e}, iters {info['iters']}", flush=True)
+    assert err < {"f32": 1e-4, "f16x3": 1e-3, "bf16x3": 5e-3}[prec]
+    if prec == "f32":
+        xs, bs, _ = _inputs(90, 2, 3, 5, np.float64)
+        ps = ciq.Problem(torch.from_numpy(xs).cuda(), "rbf", [0.5], 1.0, 1e-2)
+        out, inf2, _ = ciq.ciq_invsqrt_mvm(ps, torch.from_numpy(bs).cuda(), q=10, max_iter=300, tol=1e-10,
+                                           precond_rank=500)
+        assert inf2["converged"] and 0 < inf2["precond_rank"] <= 90
+        Ks = okern.kernel_matrix("rbf", xs, [0.5], 1.0, 1e-2)
+        O = out.cpu().numpy()
+        assert np.abs(O.T @ Ks @ O - bs.T @ bs).max() <= 1e-7 * np.abs(bs.T @ bs).max()
