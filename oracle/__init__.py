@@ -20,6 +20,8 @@ to Gaussian Processes and Bayesian Optimization", NeurIPS 2020):
 * ``precond``    -- the pivoted-Cholesky preconditioned form (Sec. 3.4,
                     Appendix D): partial pivoted Cholesky, P^{-1} and P^{1/2}
                     of P = Lbar Lbar^T + sigma^2 I, preconditioned CIQ.
+* ``posterior``  -- the Gaussian-process posterior covariance at a candidate
+                    set (Sec. 5.2, Thompson sampling) and its product.
 * ``adjoint``    -- the backward pass (Sec. 3.3) plus two independent
                     references: central finite differences and the
                     Daleckii-Krein divided-difference formula.
