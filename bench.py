@@ -145,6 +145,41 @@ def other_workload(args, torch, ciq, workloads) -> int:
                            "all_converged": all(i["converged"] for i in infos)},
                "sequential_single_calls": {"columns_per_s": cols / t_seq, "seconds": t_seq},
                "max_rel_gap_batched_vs_single": gap}
+    elif args.workload == 6:
+        # Thompson sampling (Sec. 5.2): posterior covariance root at the large
+        # workload's 50,000 points (jitter = its noise 1e-3) given 1,000
+        # observed points, S = 64 standard-normal draws, FP32 resident products
+        wl = workloads.workload(2)
+        p = wl.problems[0]
+        n_obs, obs_noise = 1000, 1e-3
+        xo_np = np.random.default_rng(2007).random((n_obs, p.d))
+        x = torch.from_numpy(p.x).to(dev).float()
+        xo = torch.from_numpy(xo_np).to(dev).float()
+        b = torch.from_numpy(p.b).to(dev).float()
+        prob = ciq.Problem(x, p.kernel, p.lengthscale, p.outputscale, p.noise)
+        kw = dict(q=wl.q, max_iter=args.max_iter, tol=args.tol, seed=4001)
+        for rep in range(2):                                            # first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out, info = ciq.ciq_posterior_mvm(prob, xo, obs_noise, b, mode="sqrt", profile=True, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        log(f"workload 6 posterior: {dt:.2f} s, {info['iters']} iterations; FP64 reference ...")
+        k = 16
+        p64 = ciq.Problem(x.double().contiguous(), p.kernel, p.lengthscale, p.outputscale, p.noise)
+        ref, rinfo = ciq.ciq_posterior_mvm(p64, xo.double().contiguous(), obs_noise, b[:, :k].double().contiguous(),
+                                           mode="sqrt", q=wl.q, max_iter=20000, tol=1e-10,
+                                           bounds=(info["lambda_min"], info["lambda_max"]))
+        emax, emed = _rel(out[:, :k], ref)
+        res = {"workload": "posterior_" + wl.name + "_obs1000", "mode": "sqrt", "precision": "f32", "t": p.n,
+               "n_obs": n_obs, "obs_noise": obs_noise, "jitter": p.noise, "d": p.d, "s": p.s, "q": wl.q,
+               "tol": args.tol, "columns_per_s": p.s / dt, "seconds": dt, "iters": info["iters"],
+               "converged": info["converged"], "kernel_cached": info["kernel_cached"],
+               "lambda_min": info["lambda_min"], "lambda_max": info["lambda_max"],
+               "mvm_ms": info["mvm_ms"] / max(info["mvm_timed"], 1),
+               "rel_err_vs_fp64": {"max": emax, "median": emed, "columns": k,
+                                   "reference": "FP64 path, same bounds, tol 1e-10",
+                                   "reference_iters": rinfo["iters"], "reference_converged": rinfo["converged"]}}
     else:
         wl = workloads.workload(5)
         p = wl.problems[0]
@@ -188,9 +223,10 @@ def main() -> int:
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
-    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5], default=2,
+    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5, 6], default=2,
                     help="2: the metric's workload (default). 3: RBF-ARD N=100,000 d=8 S=256 per precision form; "
-                         "4: 64 batched problems; 5: SVGP whitening forward + backward at M=5,000 "
+                         "4: 64 batched problems; 5: SVGP whitening forward + backward at M=5,000; "
+                         "6: Thompson-sampling posterior covariance root at 50,000 candidates, 1,000 observations "
                          "(secondary measurements, one JSON line each)")
     ap.add_argument("--precond-rank", type=int, default=0,
                     help="R > 0: pivoted-Cholesky preconditioned CIQ of rank R (the output is R B with R R^T = K, "

@@ -78,6 +78,7 @@ extern "C" {
 #define CIQ_MAX_Q   64   /* quadrature points                                       */
 #define CIQ_MAX_D   16   /* input dimensions                                        */
 #define CIQ_MAX_RANK 1024 /* preconditioner rank                                    */
+#define CIQ_MAX_OBS  4096 /* observations of ciq_posterior_mvm                       */
 
 /* One kernel matrix K = outputscale * k(X, X) + noise * I. */
 typedef struct ciq_problem {
@@ -270,6 +271,31 @@ int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts*
  */
 int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out,
                          int* piv_out, double* trace_out, hipStream_t stream);
+
+/*
+ * Posterior covariance root for Thompson sampling (Sec. 5.2): with candidates
+ * X* (cand->x, T = cand->n points) and observations X (x_obs, n_obs points)
+ * under the same kernel,
+ *   Sigma = o^2 k(X*, X*) + jitter I
+ *           - o^2 k(X*, X) (o^2 k(X, X) + obs_noise I)^{-1} o^2 k(X, X*),
+ * jitter = cand->noise, and out = Sigma^{1/2} B (mode CIQ_SQRT; a posterior
+ * sample is mean + Sigma^{1/2} eps) or Sigma^{-1/2} B (CIQ_INVSQRT) by
+ * msMINRES-CIQ exactly as ciq_sqrt_mvm / ciq_invsqrt_mvm do for K. Every
+ * product with Sigma is the candidate kernel product (on the fly or resident,
+ * any dtype) plus the FP64 low-rank correction -W (W^T v), W = Ksx L^{-T}
+ * with L L^T = Kxx + obs_noise I factored once per call on the host (so
+ * n_obs <= CIQ_MAX_OBS; the correction costs O(T n_obs s) per product). The
+ * eigenvalue floor is the jitter (Sigma - jitter I is a covariance).
+ *   x_obs: device, n_obs x cand->d, same element type as cand->x.
+ *   b, out, s, ldb, ldo, o, info: as for ciq_sqrt_mvm (no per-shift solves).
+ * Synchronous. Errors: those of ciq_sqrt_mvm; CIQ_EINVAL also for x_obs NULL,
+ * n_obs out of [1, CIQ_MAX_OBS], obs_noise < 0 or a bad mode; CIQ_ENUMERIC if
+ * Kxx + obs_noise I is not numerically positive definite; CIQ_ENOTSUP with
+ * o->precond_rank != 0.
+ */
+int ciq_posterior_mvm(const ciq_problem* cand, const void* x_obs, int n_obs, double obs_noise,
+                      int mode, const ciq_opts* o, const void* b, int s, int ldb, void* out,
+                      int ldo, ciq_info* info, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ CACHE_MODES = {"auto": CIQ_CACHE_AUTO, "off": CIQ_CACHE_OFF, "on": CIQ_CACHE_ON}
 CIQ_MAX_Q = 64
 CIQ_MAX_D = 16
 CIQ_MAX_RANK = 1024
+CIQ_MAX_OBS = 4096
 
 KERNELS = {"rbf": CIQ_KERNEL_RBF, "matern52": CIQ_KERNEL_MATERN52}
 DTYPES = {"f64": CIQ_F64, "f32": CIQ_F32, "bf16x3": CIQ_BF16X3, "f16x3": CIQ_F16X3}
@@ -118,6 +119,8 @@ PROTOTYPES = {
                                      ctypes.POINTER(ciq_info), _VP]),
     "ciq_pivoted_cholesky": (_I, [ctypes.POINTER(ciq_problem), _I, _I, _VP, ctypes.POINTER(ctypes.c_int), _PD,
                                   _VP]),
+    "ciq_posterior_mvm": (_I, [ctypes.POINTER(ciq_problem), _VP, _I, _D, _I, ctypes.POINTER(ciq_opts), _VP, _I, _I,
+                               _VP, _I, ctypes.POINTER(ciq_info), _VP]),
 }
 
 _lib = None

@@ -229,10 +229,15 @@ hipError_t launch_lr_reduce(const double* part, int nchunk, int R, int S, const 
 int lr_apply_blocks(int n);
 hipError_t launch_lr_apply(double alpha0, const double* X, int ldx, const double* A, int lda,
                            const double* T, int ldt, int n, int R, int S, double* Y, int ldy,
-                           double* dotp, const int* colmask, const int* done, hipStream_t st);
+                           double* dotp, const int* colmask, const int* done, hipStream_t st,
+                           int accumulate = 0);   // 1: Y += alpha0 X + A T
 // out[c] = sum_b dotp[b][c] (fixed order), b < nblk
 hipError_t launch_lr_dotsum(const double* dotp, int nblk, int S, double* out, const int* done,
                             hipStream_t st);
+// out[i][j] = o2 k(xa_i, xb_j), FP64 (raw coordinates, per-dimension scales
+// on the differences), out row-major with leading dimension ldo >= nb.
+hipError_t launch_xkernel(const double* xa, int na, const double* xb, int nb, int dp, int kernel, int ard,
+                          const double* scale, double o2, double* out, int ldo, hipStream_t st);
 // Preconditioned Lanczos direction: y <- (y - beta_j z_prev) - alpha_j z_cur
 // (alpha_j from colsum[0..ncol)), in place.
 hipError_t launch_pc_w(const Dev& d, double* y, const double* zc, const double* zp, hipStream_t st);

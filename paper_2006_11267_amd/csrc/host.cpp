@@ -338,6 +338,110 @@ int pc_build(const ciq_problem& p, const double* xh, int dp, int kernel, int ard
     return CIQ_OK;
 }
 
+// ---- posterior covariance at a candidate set (Sec. 5.2) ---------------------
+// Sigma = Kss + jitter I - W W^T with W = Ksx L^{-T}, L L^T = Kxx + sigma_obs^2 I
+// (Cholesky of the small observation block on the host). Every product with
+// Sigma is the candidate kernel product plus the low-rank correction
+// -W (W^T v), accumulated into the product's first partial.
+struct PostSpec {
+    const void* x_obs;   // device, n_obs x d (element type of the candidates' X)
+    int n_obs;
+    double obs_noise;
+};
+
+struct Posterior {
+    int n = 0;              // observations
+    double* W = nullptr;    // T x n
+    double* fneg = nullptr; // [n] of -1
+    double* part = nullptr; // low-rank partials
+    double* T = nullptr;    // n x max(s, n)
+    DevAlloc mem;
+};
+
+// In-place lower Cholesky factor of a row-major SPD matrix (row-oriented:
+// every inner product runs over two contiguous rows). False if not SPD.
+bool chol_lower(int n, std::vector<double>& a) {
+    for (int i = 0; i < n; ++i) {
+        double* ai = &a[(size_t)i * n];
+        for (int j = 0; j <= i; ++j) {
+            const double* aj = &a[(size_t)j * n];
+            double t = ai[j];
+            for (int k = 0; k < j; ++k) t -= ai[k] * aj[k];
+            if (i == j) {
+                if (!(t > 0.0) || !std::isfinite(t)) return false;
+                ai[i] = std::sqrt(t);
+            } else {
+                ai[j] = t / aj[j];
+            }
+        }
+    }
+    return true;
+}
+
+// mt[j][i] = (L^{-1})[i][j]: row j of mt is the forward-substitution solve of
+// L x = e_j (zero above j).
+void tri_inv_transposed(int n, const std::vector<double>& L, std::vector<double>& mt) {
+    mt.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double* x = &mt[(size_t)j * n];
+        x[j] = 1.0 / L[(size_t)j * n + j];
+        for (int i = j + 1; i < n; ++i) {
+            const double* li = &L[(size_t)i * n];
+            double t = 0.0;
+            for (int k = j; k < i; ++k) t += li[k] * x[k];
+            x[i] = -t / li[i];
+        }
+    }
+}
+
+// Sigma's correction for candidates with FP64 points xh (T x dp).
+int post_build(const ciq_problem& cand, int dtype, const double* xh, int dp, int kernel, int ard,
+               const double* scale, const PostSpec& ps, int s_cap, Posterior& po, hipStream_t st) {
+    const int T = cand.n, n = ps.n_obs;
+    po.n = n;
+    size_t part_n = 0;
+    for (int w : {s_cap, 1}) part_n = std::max(part_n, (size_t)lr_part_chunks(T, n, w) * n * w);
+    size_t off = 0;
+    double *xo = nullptr, *kxx = nullptr, *ksx = nullptr;
+    auto layout = [&](char* base) {
+        off = 0;
+        po.W = carve<double>(base, off, (size_t)T * n);
+        ksx = carve<double>(base, off, (size_t)T * n);
+        xo = carve<double>(base, off, (size_t)n * dp);
+        kxx = carve<double>(base, off, (size_t)n * n);
+        po.fneg = carve<double>(base, off, n);
+        po.part = carve<double>(base, off, part_n);
+        po.T = carve<double>(base, off, (size_t)n * std::max(s_cap, n));
+    };
+    layout(nullptr);
+    if (hipMalloc(&po.mem.p, off) != hipSuccess) {
+        (void)hipGetLastError();
+        po.mem.p = nullptr;
+        return CIQ_ENOMEM;
+    }
+    layout(static_cast<char*>(po.mem.p));
+    double ones[CIQ_MAX_D];
+    for (int k = 0; k < CIQ_MAX_D; ++k) ones[k] = 1.0;
+    if (dtype == CIQ_F64)
+        HIPCHK(launch_prep<double>(static_cast<const double*>(ps.x_obs), n, cand.d, dp, ones, xo, st));
+    else
+        HIPCHK(launch_prep<float>(static_cast<const float*>(ps.x_obs), n, cand.d, dp, ones, xo, st));
+    HIPCHK(launch_xkernel(xo, n, xo, n, dp, kernel, ard, scale, cand.outputscale, kxx, n, st));
+    HIPCHK(launch_xkernel(xh, T, xo, n, dp, kernel, ard, scale, cand.outputscale, ksx, n, st));
+    HIPCHK(launch_fill<double>(po.fneg, n, -1.0, st));
+    std::vector<double> K((size_t)n * n), mt;
+    HIPCHK(hipMemcpyAsync(K.data(), kxx, K.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) K[(size_t)i * n + i] += ps.obs_noise;
+    if (!chol_lower(n, K)) return CIQ_ENUMERIC;
+    tri_inv_transposed(n, K, mt);
+    HIPCHK(hipMemcpyAsync(po.T, mt.data(), mt.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    // W = Ksx L^{-T} (FP64 MFMA)
+    HIPCHK(launch_lr_apply(0.0, nullptr, 0, ksx, n, po.T, n, T, n, n, po.W, n, nullptr, nullptr, nullptr, st));
+    HIPCHK(hipStreamSynchronize(st));   // mt is a pageable host vector
+    return CIQ_OK;
+}
+
 // ---------------------------------------------------------------------------
 // One Krylov run over nprob problems (the single-problem calls use nprob = 1).
 // ---------------------------------------------------------------------------
@@ -352,6 +456,7 @@ struct Run {
     bool cached = false;   // products stream a resident kernel matrix (kt)
     bool precond = false;  // preconditioned run (single problem): Lanczos in the P^{-1} inner product
     const Precond* pc = nullptr;
+    const Posterior* post = nullptr;   // products with a posterior covariance (single problem)
     // device memory: points in FP64, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
     // consumes an FP32 copy q32 of the current Lanczos vector)
@@ -573,9 +678,22 @@ struct Run {
         return CIQ_OK;
     }
 
+    // Posterior covariance: the product's first partial += -W (W^T v) for the
+    // FP64 operand v (rows_total x s).
+    int post_correct(const double* v, const int* done, hipStream_t st) {
+        if (!post) return CIQ_OK;
+        const int nch = lr_part_chunks(rows_total, post->n, s);
+        HIPCHK(launch_lr_part(post->W, post->n, v, s, rows_total, post->n, s, nch, post->part, done, st));
+        HIPCHK(launch_lr_reduce(post->part, nch, post->n, s, post->fneg, post->T, s, done, st));
+        HIPCHK(launch_lr_apply(0.0, nullptr, 0, post->W, post->n, post->T, s, rows_total, post->n, s, ypart, s,
+                               nullptr, nullptr, done, st, 1));
+        return CIQ_OK;
+    }
+
     // One msMINRES iteration's kernels.
     int enqueue_iteration(int j, hipStream_t st) {
         HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
+        STCHK(post_correct(qbuf[(j - 1) & 1], &d.st->done, st));
         return enqueue_post(j, st);
     }
 
@@ -650,6 +768,7 @@ struct Run {
                     HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
                     ++pending;
                 }
+                STCHK(post_correct(qbuf[(j - 1) & 1], &d.st->done, st));
                 STCHK(enqueue_post(j, st));
                 if (j % check_every == 0 || j == max_iter) {
                     HIPCHK(hipMemcpyAsync(pinned, d.st, sizeof(IterState), hipMemcpyDeviceToHost, st));
@@ -843,7 +962,8 @@ struct ScratchLock {
 // out_ptrs[p]: n_p x s with leading dimension ldo; b_ptrs likewise with ldb.
 template <typename T>
 int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* const* b_ptrs, int s, int ldb,
-          void* const* out_ptrs, int ldo, void* solves_out, int mode, ciq_info* infos, hipStream_t st) {
+          void* const* out_ptrs, int ldo, void* solves_out, int mode, ciq_info* infos, hipStream_t st,
+          const PostSpec* post_spec = nullptr) {
     int dev;
     STCHK(get_device(&dev));
     ScratchLock lock(dev);
@@ -858,6 +978,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
     const bool precond = o->precond_rank > 0;
     Precond pc;
+    Posterior po;
 
     // ---- sizing: bounds run (s = 1, Q = 0) and main run share the points ----
     Run<T> main;
@@ -914,6 +1035,12 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
                        pc, st));
         main.pc = &pc;
         bnd.pc = &pc;
+    }
+    if (post_spec) {
+        STCHK(post_build(probs[0], dtype, main.xh, main.dp, main.kernel, main.ard, main.h_scale.data(), *post_spec,
+                         s, po, st));
+        main.post = &po;
+        bnd.post = &po;
     }
 
     std::vector<double> lmin(nprob), lmax(nprob);
@@ -1006,6 +1133,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         a.done = nullptr;
         a.prob_done = nullptr;
         HIPCHK(launch_mvm(dtype, a, st));
+        STCHK(main.post_correct(main.acc, nullptr, st));
         mvm_count += 1;
         for (int p = 0; p < nprob; ++p)
             HIPCHK(launch_reduce_splits<T>(main.ypart + (size_t)main.h_off[p] * s, main.ysplit, main.nsplit, s,
@@ -1407,6 +1535,22 @@ int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double
         return backward_impl<float>(p, o, mode, t, w, solves, g, s, ldg, db, lddb, dlengthscale, doutputscale,
                                     dnoise, info, stream);
     return CIQ_ENOTSUP;
+}
+
+int ciq_posterior_mvm(const ciq_problem* cand, const void* x_obs, int n_obs, double obs_noise, int mode,
+                      const ciq_opts* o, const void* b, int s, int ldb, void* out, int ldo, ciq_info* info,
+                      hipStream_t stream) {
+    const int rc = check_solve_args(cand, o, b, s, ldb, out, ldo, info);
+    if (rc != CIQ_OK) return rc;
+    if (!x_obs || n_obs < 1 || n_obs > CIQ_MAX_OBS || !(obs_noise >= 0.0) || !std::isfinite(obs_noise))
+        return CIQ_EINVAL;
+    if (mode != CIQ_INVSQRT && mode != CIQ_SQRT) return CIQ_EINVAL;
+    if (o->precond_rank != 0) return CIQ_ENOTSUP;
+    const PostSpec ps{x_obs, n_obs, obs_noise};
+    const void* bp[1] = {b};
+    void* op[1] = {out};
+    if (o->dtype == CIQ_F64) return solve<double>(1, cand, o, bp, s, ldb, op, ldo, nullptr, mode, info, stream, &ps);
+    return solve<float>(1, cand, o, bp, s, ldb, op, ldo, nullptr, mode, info, stream, &ps);
 }
 
 int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out, int* piv_out,

@@ -278,7 +278,8 @@ __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const doub
                                                        const double* __restrict__ A, int lda,
                                                        const double* __restrict__ T, int ldt, int n, int R, int S,
                                                        double* Y, int ldy, double* __restrict__ dotp,
-                                                       const int* __restrict__ colmask, const int* done) {
+                                                       const int* __restrict__ colmask, const int* done,
+                                                       int accumulate) {
     if (done != nullptr && *done) return;
     __shared__ double red[16][64];
     const int tid = threadIdx.x;
@@ -332,7 +333,8 @@ __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const doub
             const int i = i0 + wave * 16 + lk + 4 * v;
             if (i >= n) continue;
             const double x = (X != nullptr) ? X[(long long)i * ldx + c] : 0.0;
-            const double y = alpha0 * x + acc[sb][v];
+            double y = alpha0 * x + acc[sb][v];
+            if (accumulate) y += Y[(long long)i * ldy + c];
             Y[(long long)i * ldy + c] = y;
             dsum[sb] = fma(x, y, dsum[sb]);
         }
@@ -370,6 +372,34 @@ __global__ __launch_bounds__(1024) void lr_dotsum_kernel(const double* __restric
         for (int k = 0; k < 16; ++k) sum += red[k][cl];
         out[c] = sum;
     }
+}
+
+struct XScale {
+    double v[CIQ_MAX_D];
+};
+
+// Cross-kernel matrix out[i][j] = o2 k(xa_i, xb_j) (FP64; raw coordinates,
+// per-dimension scales on the differences as in every product). One thread
+// per entry, j fastest (coalesced writes).
+template <int KERNEL, bool ARD>
+__global__ __launch_bounds__(256) void xkernel_kernel(const double* __restrict__ xa, int na,
+                                                      const double* __restrict__ xb, int nb, int dp, XScale sc,
+                                                      double o2, double* __restrict__ out, int ldo) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)na * nb) return;
+    const int i = (int)(e / nb), j = (int)(e - (long long)i * nb);
+    double r2 = 0.0;
+    for (int k = 0; k < dp; ++k) {
+        const double dd = xa[(long long)i * dp + k] - xb[(long long)j * dp + k];
+        if constexpr (ARD) {
+            const double u = dd * sc.v[k];
+            r2 = fma(u, u, r2);
+        } else {
+            r2 = fma(dd, dd, r2);
+        }
+    }
+    if constexpr (!ARD) r2 *= sc.v[0] * sc.v[0];
+    out[(long long)i * ldo + j] = o2 * mfma::kentry64<KERNEL>(r2);
 }
 
 // Single-problem runs only (the preconditioned path is not batched).
@@ -439,15 +469,31 @@ int lr_apply_blocks(int n) { return (n + 63) / 64; }
 
 hipError_t launch_lr_apply(double alpha0, const double* X, int ldx, const double* A, int lda, const double* T,
                            int ldt, int n, int R, int S, double* Y, int ldy, double* dotp, const int* colmask,
-                           const int* done, hipStream_t st) {
+                           const int* done, hipStream_t st, int accumulate) {
     dim3 grid(lr_apply_blocks(n), (S + 63) / 64);
     hipLaunchKernelGGL(lr_apply_kernel, grid, dim3(256), 0, st, alpha0, X, ldx, A, lda, T, ldt, n, R, S, Y, ldy,
-                       dotp, colmask, done);
+                       dotp, colmask, done, accumulate);
     return hipGetLastError();
 }
 
 hipError_t launch_lr_dotsum(const double* dotp, int nblk, int S, double* out, const int* done, hipStream_t st) {
     hipLaunchKernelGGL(lr_dotsum_kernel, dim3((S + 63) / 64), dim3(1024), 0, st, dotp, nblk, S, out, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_xkernel(const double* xa, int na, const double* xb, int nb, int dp, int kernel, int ard,
+                          const double* scale, double o2, double* out, int ldo, hipStream_t st) {
+    XScale sc;
+    for (int k = 0; k < CIQ_MAX_D; ++k) sc.v[k] = scale[k];
+    const long long total = (long long)na * nb;
+    const dim3 g((unsigned)((total + 255) / 256)), b(256);
+    if (kernel == CIQ_KERNEL_RBF) {
+        if (ard) hipLaunchKernelGGL((xkernel_kernel<CIQ_KERNEL_RBF, true>), g, b, 0, st, xa, na, xb, nb, dp, sc, o2, out, ldo);
+        else hipLaunchKernelGGL((xkernel_kernel<CIQ_KERNEL_RBF, false>), g, b, 0, st, xa, na, xb, nb, dp, sc, o2, out, ldo);
+    } else {
+        if (ard) hipLaunchKernelGGL((xkernel_kernel<CIQ_KERNEL_MATERN52, true>), g, b, 0, st, xa, na, xb, nb, dp, sc, o2, out, ldo);
+        else hipLaunchKernelGGL((xkernel_kernel<CIQ_KERNEL_MATERN52, false>), g, b, 0, st, xa, na, xb, nb, dp, sc, o2, out, ldo);
+    }
     return hipGetLastError();
 }
 

@@ -158,6 +158,36 @@ def ciq_sqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int =
                   lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank)
 
 
+def ciq_posterior_mvm(candidates: Problem, x_obs: torch.Tensor, obs_noise: float, b: torch.Tensor,
+                      mode: str = "sqrt", q: int = 15, max_iter: int = 200, tol: float = 1e-4,
+                      precision: Optional[str] = None, bounds=None, lanczos_steps: int = 0, seed: int = 0,
+                      check_every: int = 0, profile: bool = False, kernel_cache: str = "auto",
+                      cache_budget_mib: int = 0, graph: bool = False):
+    """Sigma^{1/2} B (mode "sqrt") or Sigma^{-1/2} B ("invsqrt") for the GP
+    posterior covariance at the candidates given observations at x_obs
+    (candidates.noise is the jitter) -> (out, info)."""
+    lib = L.load()
+    code = _dtype_code(candidates.x, precision)
+    if not (x_obs.is_cuda and x_obs.dim() == 2 and x_obs.is_contiguous() and x_obs.dtype == candidates.x.dtype):
+        raise ValueError("x_obs must be a contiguous 2-D device tensor of the candidates' dtype")
+    b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+    if b2.stride(1) != 1:
+        b2 = b2.contiguous()
+    n, s = b2.shape
+    out = torch.empty((n, s), dtype=_elem_dtype(code), device=b.device)
+    p, keep = candidates.c_struct()
+    o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, kernel_cache,
+              cache_budget_mib, graph)
+    info = L.ciq_info()
+    mode_code = L.CIQ_SQRT if mode == "sqrt" else L.CIQ_INVSQRT
+    L.check(lib.ciq_posterior_mvm(ctypes.byref(p), ctypes.c_void_p(x_obs.data_ptr()), x_obs.shape[0],
+                                  float(obs_noise), mode_code, ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s,
+                                  b2.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0), ctypes.byref(info),
+                                  _stream()), "ciq_posterior_mvm")
+    del keep
+    return out.reshape(b.shape), info.as_dict()
+
+
 def ciq_pivoted_cholesky(problem: Problem, rank: int):
     """Rank-`rank` partial pivoted Cholesky factor of outputscale * k(X, X):
     (Lbar as an n x rank float64 device tensor, pivots (numpy, -1 after a

@@ -196,6 +196,22 @@ def test_preconditioner_arguments_rejected(lib):
     del keep, keep0
 
 
+def test_posterior_arguments_rejected(lib):
+    p, keep = _bad_problem()
+    o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4)
+    info = L.ciq_info()
+    fake = ctypes.c_void_p(512)
+    args = dict(x=fake, n=5, noise=1e-2, mode=L.CIQ_SQRT)
+    for bad in [dict(x=None), dict(n=0), dict(n=4097), dict(noise=-1.0), dict(noise=float("nan")), dict(mode=7)]:
+        a = {**args, **bad}
+        assert lib.ciq_posterior_mvm(ctypes.byref(p), a["x"], a["n"], a["noise"], a["mode"], ctypes.byref(o), fake,
+                                     2, 2, fake, 2, ctypes.byref(info), None) == L.CIQ_EINVAL, bad
+    o.precond_rank = 4
+    assert lib.ciq_posterior_mvm(ctypes.byref(p), fake, 5, 1e-2, L.CIQ_SQRT, ctypes.byref(o), fake, 2, 2, fake, 2,
+                                 ctypes.byref(info), None) == L.CIQ_ENOTSUP
+    del keep
+
+
 def test_strerror(lib):
     for code in range(6):
         assert lib.ciq_strerror(code)
