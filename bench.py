@@ -180,6 +180,35 @@ def other_workload(args, torch, ciq, workloads) -> int:
                "rel_err_vs_fp64": {"max": emax, "median": emed, "columns": k,
                                    "reference": "FP64 path, same bounds, tol 1e-10",
                                    "reference_iters": rinfo["iters"], "reference_converged": rinfo["converged"]}}
+    elif args.workload == 7:
+        # Gibbs sampler of the image model (Sec. 5.3): A^{-1/2} eps for the
+        # 25,600 x 25,600 precision of a 160 x 160 image observed as four
+        # 80 x 80 blurred, decimated images (g_obs = 1, g_prior = 0.01)
+        from workloads import gibbs
+        A = gibbs.gibbs_precision(160, 1.0, 0.01)
+        csr = (torch.from_numpy(A.indptr.astype(np.int32)).to(dev), torch.from_numpy(A.indices.astype(np.int32)).to(dev),
+               torch.from_numpy(A.data).to(dev))
+        n = A.shape[0]
+        res = {"workload": "gibbs_image160_obs4x80", "mode": "invsqrt", "precision": "f64", "n": n, "nnz": int(A.nnz),
+               "q": 15, "tol": 1e-6, "max_iter": 400, "runs": []}
+        for s, graph in ((1, False), (1, True), (64, False)):
+            b = torch.from_numpy(workloads.gaussian_rhs(n, s, 7002, dtype=np.float64)).to(dev)
+            kw = dict(q=15, max_iter=400, tol=1e-6, seed=7004, graph=graph)
+            ciq.ciq_csr_mvm(*csr, b, **kw)                              # warm-up
+            torch.cuda.synchronize()
+            reps = 20 if s == 1 else 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out, info = ciq.ciq_csr_mvm(*csr, b, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            ref, rinfo = ciq.ciq_csr_mvm(*csr, b, q=15, max_iter=4000, tol=1e-12,
+                                         bounds=(info["lambda_min"], info["lambda_max"]))
+            emax, _ = _rel(out, ref)
+            res["runs"].append({"s": s, "graph": graph, "samples_per_s": s / dt, "ms_per_call": 1e3 * dt,
+                                "iters": info["iters"], "converged": info["converged"], "max_rel_err": emax})
+            log(f"workload 7 s={s} graph={graph}: {1e3 * dt:.2f} ms per call, {info['iters']} iterations, "
+                f"err {emax:.1e}")
     else:
         wl = workloads.workload(5)
         p = wl.problems[0]
@@ -223,10 +252,11 @@ def main() -> int:
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
-    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5, 6], default=2,
+    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5, 6, 7], default=2,
                     help="2: the metric's workload (default). 3: RBF-ARD N=100,000 d=8 S=256 per precision form; "
                          "4: 64 batched problems; 5: SVGP whitening forward + backward at M=5,000; "
-                         "6: Thompson-sampling posterior covariance root at 50,000 candidates, 1,000 observations "
+                         "6: Thompson-sampling posterior covariance root at 50,000 candidates, 1,000 observations; "
+                         "7: Gibbs image-model sample, 25,600-dimensional sparse precision "
                          "(secondary measurements, one JSON line each)")
     ap.add_argument("--precond-rank", type=int, default=0,
                     help="R > 0: pivoted-Cholesky preconditioned CIQ of rank R (the output is R B with R R^T = K, "

@@ -92,6 +92,15 @@ typedef struct ciq_problem {
     double noise;              /* sigma^2 >= 0 (diagonal only)                      */
 } ciq_problem;
 
+/* A sparse symmetric matrix in CSR form (device arrays, FP64 values). */
+typedef struct ciq_csr {
+    int32_t n;                 /* rows = columns, >= 1                              */
+    int32_t nnz;               /* stored entries                                    */
+    const int32_t* row_ptr;    /* device, n + 1 offsets into col_idx / val          */
+    const int32_t* col_idx;    /* device, nnz column indices (0-based)              */
+    const double* val;         /* device, nnz values                                */
+} ciq_csr;
+
 /* Solver options. Zero-initialise and set what you need. */
 typedef struct ciq_opts {
     int32_t dtype;             /* CIQ_F64 / CIQ_F32 / CIQ_BF16X3 / CIQ_F16X3        */
@@ -271,6 +280,25 @@ int ciq_invsqrt_mvm_batched(int nprob, const ciq_problem* probs, const ciq_opts*
  */
 int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out,
                          int* piv_out, double* trace_out, hipStream_t stream);
+
+/*
+ * msMINRES-CIQ with a caller's sparse symmetric positive-definite operator A
+ * in place of the kernel matrix (the structured operators of Sec. 5.3, e.g.
+ * the precision g_obs A^T A + g_prior L of an image model, whose Gibbs
+ * sampler draws mean + A^{-1/2} eps): out = A^{-1/2} B (mode CIQ_INVSQRT) or
+ * A^{1/2} B (CIQ_SQRT). Products are one FP64 CSR product per iteration
+ * (entries of each row in storage order); everything else as for
+ * ciq_invsqrt_mvm. Without given bounds the Lanczos estimate uses
+ * lambda_min = theta_min / 2 (no known floor). Symmetry and definiteness are
+ * the caller's (not checked; a violation shows as non-convergence or
+ * CIQ_ENUMERIC).
+ *   a: host struct of device arrays; b, out: device n x s doubles.
+ * Synchronous. Errors: CIQ_EINVAL (a, its arrays, n, mode, and the checks of
+ * ciq_invsqrt_mvm); CIQ_ENOTSUP unless o->dtype == CIQ_F64 and
+ * o->precond_rank == 0.
+ */
+int ciq_csr_mvm(const ciq_csr* a, int mode, const ciq_opts* o, const double* b, int s, int ldb,
+                double* out, int ldo, ciq_info* info, hipStream_t stream);
 
 /*
  * Posterior covariance root for Thompson sampling (Sec. 5.2): with candidates

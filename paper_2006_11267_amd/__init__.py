@@ -7,6 +7,7 @@ and the current stream); all computation runs in the library.
 from ._lib import CIQError, load  # noqa: F401
 from .ops import (  # noqa: F401
     Problem,
+    ciq_csr_mvm,
     ciq_eig_bounds,
     ciq_invsqrt_mvm,
     ciq_invsqrt_mvm_batched,

@@ -39,6 +39,16 @@ class ciq_problem(ctypes.Structure):
     ]
 
 
+class ciq_csr(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("nnz", ctypes.c_int32),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
+
+
 class ciq_opts(ctypes.Structure):
     _fields_ = [
         ("dtype", ctypes.c_int32),
@@ -119,6 +129,8 @@ PROTOTYPES = {
                                      ctypes.POINTER(ciq_info), _VP]),
     "ciq_pivoted_cholesky": (_I, [ctypes.POINTER(ciq_problem), _I, _I, _VP, ctypes.POINTER(ctypes.c_int), _PD,
                                   _VP]),
+    "ciq_csr_mvm": (_I, [ctypes.POINTER(ciq_csr), _I, ctypes.POINTER(ciq_opts), _VP, _I, _I, _VP, _I,
+                         ctypes.POINTER(ciq_info), _VP]),
     "ciq_posterior_mvm": (_I, [ctypes.POINTER(ciq_problem), _VP, _I, _D, _I, ctypes.POINTER(ciq_opts), _VP, _I, _I,
                                _VP, _I, ctypes.POINTER(ciq_info), _VP]),
 }

@@ -238,6 +238,17 @@ hipError_t launch_lr_dotsum(const double* dotp, int nblk, int S, double* out, co
 // on the differences), out row-major with leading dimension ldo >= nb.
 hipError_t launch_xkernel(const double* xa, int na, const double* xb, int nb, int dp, int kernel, int ard,
                           const double* scale, double o2, double* out, int ldo, hipStream_t st);
+// ---- sparse symmetric operator (sparse.hip) ----------------------------------
+struct SparseOp {
+    int n;                   // rows = columns
+    const int* row_ptr;      // [n + 1]
+    const int* col;          // [nnz]
+    const double* val;       // [nnz]
+};
+// y = A x for s columns (x: n x s, ld ldx; y: n x s, ld ldy); `done` as above.
+hipError_t launch_spmv(const SparseOp& a, const double* x, int ldx, int s, double* y, int ldy, const int* done,
+                       hipStream_t st);
+
 // Preconditioned Lanczos direction: y <- (y - beta_j z_prev) - alpha_j z_cur
 // (alpha_j from colsum[0..ncol)), in place.
 hipError_t launch_pc_w(const Dev& d, double* y, const double* zc, const double* zp, hipStream_t st);

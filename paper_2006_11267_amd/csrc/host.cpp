@@ -457,6 +457,7 @@ struct Run {
     bool precond = false;  // preconditioned run (single problem): Lanczos in the P^{-1} inner product
     const Precond* pc = nullptr;
     const Posterior* post = nullptr;   // products with a posterior covariance (single problem)
+    const SparseOp* sp = nullptr;      // products with a caller's sparse operator (single problem, FP64)
     // device memory: points in FP64, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
     // consumes an FP32 copy q32 of the current Lanczos vector)
@@ -558,6 +559,7 @@ struct Run {
         nsplit = mvm_pick_nsplit(dtype, nrb, max_n, s);
         if (cached && (max_n + 63) / 64 >= 8 && nrb * 8 >= 512)
             nsplit = 8;   // one column range per XCD (split = block index mod 8)
+        if (sp) nsplit = 1;   // the sparse product writes one partial
         ysplit = (long long)rows_total * s;
     }
 
@@ -690,9 +692,19 @@ struct Run {
         return CIQ_OK;
     }
 
+    // The product of iteration j (kernel matrix, or the caller's sparse operator).
+    int product(int j, hipStream_t st) {
+        if (sp) {
+            HIPCHK(launch_spmv(*sp, qbuf[(j - 1) & 1], s, s, ypart, s, &d.st->done, st));
+            return CIQ_OK;
+        }
+        HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
+        return CIQ_OK;
+    }
+
     // One msMINRES iteration's kernels.
     int enqueue_iteration(int j, hipStream_t st) {
-        HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
+        STCHK(product(j, st));
         STCHK(post_correct(qbuf[(j - 1) & 1], &d.st->done, st));
         return enqueue_post(j, st);
     }
@@ -763,7 +775,7 @@ struct Run {
             while (j <= max_iter) {
                 const bool timed = ev_pool != nullptr && pending < n_ev;
                 if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
-                HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
+                STCHK(product(j, st));
                 if (timed) {
                     HIPCHK(hipEventRecord(ev_pool[2 * pending + 1], st));
                     ++pending;
@@ -806,6 +818,10 @@ struct Run {
 // product's input type; the timed launches write only the partial buffer.
 template <typename T>
 int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
+    if (r.sp) {
+        r.configure(1);
+        return CIQ_OK;
+    }
     const int nsb = (std::min(r.s, product_cap(r.dtype, r.cached)) + 15) / 16;
     if ((r.dtype == CIQ_F32 && nsb >= 8) || r.dtype == CIQ_BF16X3 || r.dtype == CIQ_F16X3) {
         r.configure(1);
@@ -963,7 +979,7 @@ struct ScratchLock {
 template <typename T>
 int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* const* b_ptrs, int s, int ldb,
           void* const* out_ptrs, int ldo, void* solves_out, int mode, ciq_info* infos, hipStream_t st,
-          const PostSpec* post_spec = nullptr) {
+          const PostSpec* post_spec = nullptr, const SparseOp* sparse = nullptr) {
     int dev;
     STCHK(get_device(&dev));
     ScratchLock lock(dev);
@@ -975,7 +991,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     const bool profile = o->profile != 0;
 
     KCache kc;
-    STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
+    if (!sparse) STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
     const bool precond = o->precond_rank > 0;
     Precond pc;
     Posterior po;
@@ -985,6 +1001,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     fill_problem_tables(main, probs, nprob, dtype);
     main.cached = (kc.ptr != nullptr);
     main.precond = precond;
+    main.sp = sparse;
     main.dtype = dtype;
     main.s = s;
     main.Q = o->q;
@@ -1003,6 +1020,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     bnd.bounds_mode = 1;
     bnd.cached = main.cached;
     bnd.precond = precond;
+    bnd.sp = sparse;
     bnd.plan(2);
 
     Sizer sz;
@@ -1026,7 +1044,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     bnd.fill_dev();
 
     STCHK(main.upload_tables(st));
-    STCHK(setup_points(main, probs, dtype, st));
+    if (!sparse) STCHK(setup_points(main, probs, dtype, st));
     STCHK(kcache_build(main, kc, st));
     bnd.kt = main.kt;
     bnd.njs = main.njs;
@@ -1132,7 +1150,10 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         MvmArgs a = main.mvm_args(operand, main.ypart);
         a.done = nullptr;
         a.prob_done = nullptr;
-        HIPCHK(launch_mvm(dtype, a, st));
+        if (sparse)
+            HIPCHK(launch_spmv(*sparse, main.acc, s, s, main.ypart, s, nullptr, st));
+        else
+            HIPCHK(launch_mvm(dtype, a, st));
         STCHK(main.post_correct(main.acc, nullptr, st));
         mvm_count += 1;
         for (int p = 0; p < nprob; ++p)
@@ -1551,6 +1572,30 @@ int ciq_posterior_mvm(const ciq_problem* cand, const void* x_obs, int n_obs, dou
     void* op[1] = {out};
     if (o->dtype == CIQ_F64) return solve<double>(1, cand, o, bp, s, ldb, op, ldo, nullptr, mode, info, stream, &ps);
     return solve<float>(1, cand, o, bp, s, ldb, op, ldo, nullptr, mode, info, stream, &ps);
+}
+
+int ciq_csr_mvm(const ciq_csr* a, int mode, const ciq_opts* o, const double* b, int s, int ldb, double* out,
+                int ldo, ciq_info* info, hipStream_t stream) {
+    if (!a || !a->row_ptr || !a->col_idx || !a->val || a->n < 1 || a->nnz < 0) return CIQ_EINVAL;
+    if (mode != CIQ_INVSQRT && mode != CIQ_SQRT) return CIQ_EINVAL;
+    // validate the options and sizes through the common check with a stand-in problem of n points
+    const double one = 1.0;
+    ciq_problem p{};
+    p.n = a->n;
+    p.d = 1;
+    p.x = a->val;            // never read: the sparse operator replaces the kernel product
+    p.kernel = CIQ_KERNEL_RBF;
+    p.n_lengthscale = 1;
+    p.lengthscale = &one;
+    p.outputscale = 1.0;
+    p.noise = 0.0;
+    const int rc = check_solve_args(&p, o, b, s, ldb, out, ldo, info);
+    if (rc != CIQ_OK) return rc;
+    if (o->dtype != CIQ_F64 || o->precond_rank != 0) return CIQ_ENOTSUP;
+    const SparseOp sp{a->n, a->row_ptr, a->col_idx, a->val};
+    const void* bp[1] = {b};
+    void* op[1] = {out};
+    return solve<double>(1, &p, o, bp, s, ldb, op, ldo, nullptr, mode, info, stream, nullptr, &sp);
 }
 
 int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out, int* piv_out,

@@ -1,0 +1,41 @@
+// Products with a caller-supplied sparse symmetric operator (CSR, FP64): the
+// structured-operator form of msMINRES-CIQ (Sec. 5.3 applies it to the
+// precision of an image model). The Krylov machinery is unchanged; only the
+// product is this kernel instead of the kernel-matrix product.
+#include <hip/hip_runtime.h>
+
+#include "ciq_internal.h"
+
+namespace ciq {
+
+namespace {
+
+// y[i][c] = sum_k val[k] x[col[k]][c] over row i's entries. Block: TS columns
+// x RL rows (TS = the power of two >= s, at most 64); each thread one (row,
+// column), entries in storage order (deterministic).
+__global__ __launch_bounds__(256) void spmv_kernel(SparseOp a, const double* __restrict__ x, int ldx, int s,
+                                                   double* __restrict__ y, int ldy, int TS, const int* done) {
+    if (done != nullptr && *done) return;
+    const int RL = 256 / TS;
+    const int cl = threadIdx.x % TS, rl = threadIdx.x / TS;
+    const int row = blockIdx.x * RL + rl, c = blockIdx.y * TS + cl;
+    if (row >= a.n || c >= s) return;
+    double acc = 0.0;
+    const int k1 = a.row_ptr[row + 1];
+    for (int k = a.row_ptr[row]; k < k1; ++k) acc = fma(a.val[k], x[(long long)a.col[k] * ldx + c], acc);
+    y[(long long)row * ldy + c] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_spmv(const SparseOp& a, const double* x, int ldx, int s, double* y, int ldy, const int* done,
+                       hipStream_t st) {
+    int TS = 1;
+    while (TS < s && TS < 64) TS <<= 1;
+    const int RL = 256 / TS;
+    dim3 grid((a.n + RL - 1) / RL, (s + TS - 1) / TS);
+    hipLaunchKernelGGL(spmv_kernel, grid, dim3(256), 0, st, a, x, ldx, s, y, ldy, TS, done);
+    return hipGetLastError();
+}
+
+}  // namespace ciq

@@ -188,6 +188,34 @@ def ciq_posterior_mvm(candidates: Problem, x_obs: torch.Tensor, obs_noise: float
     return out.reshape(b.shape), info.as_dict()
 
 
+def ciq_csr_mvm(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, b: torch.Tensor,
+                mode: str = "invsqrt", q: int = 15, max_iter: int = 400, tol: float = 1e-4, bounds=None,
+                lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
+                graph: bool = False):
+    """A^{-1/2} B ("invsqrt") or A^{1/2} B ("sqrt") for a sparse symmetric
+    positive-definite A given in CSR form (int32 indices, float64 values,
+    device tensors) -> (out, info)."""
+    lib = L.load()
+    for t_, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (val, torch.float64), (b, torch.float64)):
+        if not (t_.is_cuda and t_.dtype == dt):
+            raise ValueError("row_ptr/col_idx: int32, val/b: float64, all device tensors")
+    n = row_ptr.numel() - 1
+    b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+    if b2.stride(1) != 1:
+        b2 = b2.contiguous()
+    s = b2.shape[1]
+    out = torch.empty((n, s), dtype=torch.float64, device=b.device)
+    a = L.ciq_csr(n=n, nnz=col_idx.numel(), row_ptr=ctypes.c_void_p(row_ptr.data_ptr()),
+                  col_idx=ctypes.c_void_p(col_idx.data_ptr()), val=ctypes.c_void_p(val.data_ptr()))
+    o = _opts(L.CIQ_F64, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, graph=graph)
+    info = L.ciq_info()
+    mode_code = L.CIQ_SQRT if mode == "sqrt" else L.CIQ_INVSQRT
+    L.check(lib.ciq_csr_mvm(ctypes.byref(a), mode_code, ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s,
+                            b2.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0), ctypes.byref(info),
+                            _stream()), "ciq_csr_mvm")
+    return out.reshape(b.shape), info.as_dict()
+
+
 def ciq_pivoted_cholesky(problem: Problem, rank: int):
     """Rank-`rank` partial pivoted Cholesky factor of outputscale * k(X, X):
     (Lbar as an n x rank float64 device tensor, pivots (numpy, -1 after a

@@ -212,6 +212,25 @@ def test_posterior_arguments_rejected(lib):
     del keep
 
 
+def test_csr_arguments_rejected(lib):
+    fake = ctypes.c_void_p(512)
+    info = L.ciq_info()
+    o = L.ciq_opts(dtype=L.CIQ_F64, q=8, max_iter=10, tol=1e-4)
+    good = dict(n=10, nnz=30, row_ptr=fake, col_idx=fake, val=fake)
+    for bad in [dict(n=0), dict(nnz=-1), dict(row_ptr=None), dict(col_idx=None), dict(val=None)]:
+        a = L.ciq_csr(**{**good, **bad})
+        assert lib.ciq_csr_mvm(ctypes.byref(a), L.CIQ_INVSQRT, ctypes.byref(o), fake, 2, 2, fake, 2,
+                               ctypes.byref(info), None) == L.CIQ_EINVAL, bad
+    a = L.ciq_csr(**good)
+    assert lib.ciq_csr_mvm(ctypes.byref(a), 5, ctypes.byref(o), fake, 2, 2, fake, 2, ctypes.byref(info),
+                           None) == L.CIQ_EINVAL
+    assert lib.ciq_csr_mvm(ctypes.byref(a), L.CIQ_SQRT, ctypes.byref(o), fake, 2, 1, fake, 2, ctypes.byref(info),
+                           None) == L.CIQ_EINVAL
+    o32 = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4)
+    assert lib.ciq_csr_mvm(ctypes.byref(a), L.CIQ_SQRT, ctypes.byref(o32), fake, 2, 2, fake, 2, ctypes.byref(info),
+                           None) == L.CIQ_ENOTSUP
+
+
 def test_strerror(lib):
     for code in range(6):
         assert lib.ciq_strerror(code)

@@ -1,0 +1,74 @@
+"""msMINRES-CIQ with a sparse operator (ciq_csr_mvm): the Gibbs image model's
+precision (Sec. 5.3) against the oracle's CIQ with the same matrix, at fixed
+small J and converged, up to the paper's full 25,600-dimensional size."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, ciq_module, colwise_rel, torch_cuda
+from oracle import ciq as oc
+from workloads import gibbs
+
+pytestmark = pytest.mark.gpu
+
+
+def _device_csr(torch, A):
+    return (torch.from_numpy(A.indptr.astype(np.int32)).cuda(), torch.from_numpy(A.indices.astype(np.int32)).cuda(),
+            torch.from_numpy(A.data.astype(np.float64)).cuda())
+
+
+def _rhs(n, s, seed):
+    return np.random.default_rng(seed).standard_normal((n, s))
+
+
+@pytest.mark.parametrize("J", [1, 5])
+@pytest.mark.parametrize("mode", ["invsqrt", "sqrt"])
+def test_csr_small_j_parity(mode, J):
+    """24 x 24 image (576 unknowns), S = 5, same bounds, fixed J: agreement to
+    rounding (bar: 10x the oracle's move under one-ulp perturbations of the
+    stored values)."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    A = gibbs.gibbs_precision(24, 1.0, 0.01)
+    lam = np.linalg.eigvalsh(A.toarray())
+    bounds = (lam[0], lam[-1])
+    b = _rhs(A.shape[0], 5, 3)
+    announce(f"csr small-J parity {mode} J={J}")
+    out, info = ciq.ciq_csr_mvm(*_device_csr(torch, A), torch.from_numpy(b).cuda(), mode=mode, q=10, max_iter=J,
+                                tol=0.0, bounds=bounds)
+    ref, _ = oc.ciq(lambda v: A @ v, b, bounds[0], bounds[1], 10, J, 0.0, mode)
+    spread = 0.0
+    for seed in range(2):
+        Ap = A.copy()
+        Ap.data = Ap.data * (1.0 + 2.2e-16 * np.random.default_rng(70 + seed).standard_normal(Ap.data.size))
+        Ap = (0.5 * (Ap + Ap.T)).tocsr()
+        alt, _ = oc.ciq(lambda v: Ap @ v, b, bounds[0], bounds[1], 10, J, 0.0, mode)
+        spread = max(spread, colwise_rel(alt, ref).max())
+    bar = max(10.0 * spread, 1e-12)
+    gap = colwise_rel(out.cpu().numpy(), ref).max()
+    print(f"gap {gap:.2e} bar {bar:.2e}", flush=True)
+    assert info["iters"] == J and gap < bar
+
+
+@pytest.mark.parametrize("n_img,s", [(24, 3), (160, 4)])
+def test_csr_converged_parity(n_img, s):
+    """Converged (tol 1e-10; the library's own bounds, handed to the oracle)
+    at 576 and at the paper's 25,600 unknowns (160 x 160 image, 4 low-res
+    images of 80 x 80): both modes to 1e-8; a zero column stays zero."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    A = gibbs.gibbs_precision(n_img, 1.0, 0.01)
+    b = _rhs(A.shape[0], s, n_img)
+    b[:, 1] = 0.0
+    csr = _device_csr(torch, A)
+    announce(f"csr converged parity {n_img}x{n_img} s={s}")
+    for mode in ("invsqrt", "sqrt"):
+        out, info = ciq.ciq_csr_mvm(*csr, torch.from_numpy(b).cuda(), mode=mode, q=15, max_iter=2000, tol=1e-10)
+        assert info["converged"]
+        ref, oinfo = oc.ciq(lambda v: A @ v, b, info["lambda_min"], info["lambda_max"], 15, 2000, 1e-10, mode)
+        o = out.cpu().numpy()
+        assert np.all(o[:, 1] == 0.0)
+        keep = [0] + list(range(2, s))
+        err = colwise_rel(o[:, keep], ref[:, keep]).max()
+        print(f"{mode}: rel err {err:.2e}, iters {info['iters']} (oracle {oinfo.iters}), bounds "
+              f"{info['lambda_min']:.3g} {info['lambda_max']:.3g}", flush=True)
+        assert err < 1e-8
