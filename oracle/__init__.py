@@ -22,6 +22,8 @@ to Gaussian Processes and Bayesian Optimization", NeurIPS 2020):
                     of P = Lbar Lbar^T + sigma^2 I, preconditioned CIQ.
 * ``posterior``  -- the Gaussian-process posterior covariance at a candidate
                     set (Sec. 5.2, Thompson sampling) and its product.
+* ``svgp``       -- the CIQ-whitened SVGP predictive distribution in natural
+                    parameters (Sec. 5.1, App. E).
 * ``adjoint``    -- the backward pass (Sec. 3.3) plus two independent
                     references: central finite differences and the
                     Daleckii-Krein divided-difference formula.
