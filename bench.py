@@ -209,6 +209,35 @@ def other_workload(args, torch, ciq, workloads) -> int:
                                 "iters": info["iters"], "converged": info["converged"], "max_rel_err": emax})
             log(f"workload 7 s={s} graph={graph}: {1e3 * dt:.2f} ms per call, {info['iters']} iterations, "
                 f"err {emax:.1e}")
+    elif args.workload == 8:
+        # SVGP predictive pass (Sec. 5.1, App. E) at M = 10,000 inducing points
+        # (workload 5's RBF-ARD kernel on [0,1]^10, jitter 1e-4), a minibatch of
+        # 256 test points, natural parameters theta ~ N(0, 1),
+        # Theta = -(I + H H^T / k) / 2 with H ~ N(0, 1) of width k = 64
+        wl = workloads.workload(5)
+        p = wl.problems[0]
+        M, nb, k = 10000, 256, 64
+        rng = np.random.default_rng(8001)
+        z = torch.from_numpy(rng.random((M, p.d)).astype(np.float32)).to(dev)
+        x = torch.from_numpy(rng.random((nb, p.d)).astype(np.float32)).to(dev)
+        H = rng.standard_normal((M, k))
+        Theta = -0.5 * (np.eye(M) + H @ H.T / k)
+        theta = torch.from_numpy(rng.standard_normal(M)).to(dev)
+        Theta = torch.from_numpy(Theta).to(dev)
+        prob = ciq.Problem(z, p.kernel, p.lengthscale, p.outputscale, p.noise)
+        kw = dict(q=wl.q, max_iter=1000, tol=1e-4, solve_max_iter=500, solve_tol=1e-6)
+        for rep in range(2):                                            # first pass warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mean, var, _, info, info_s = ciq.ciq_svgp_predict(prob, x, theta, Theta, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        res = {"workload": "svgp_predict_m10000_d10_b256", "precision": "f32", "m": M, "batch": nb, "d": p.d,
+               "q": wl.q, "tol": 1e-4, "seconds": dt, "test_points_per_s": nb / dt, "ciq_iters": info["iters"],
+               "ciq_converged": info["converged"], "kernel_cached": info["kernel_cached"],
+               "solve_iters": info_s["iters"], "solve_converged": info_s["converged"],
+               "var_min": float(var.min()), "var_max": float(var.max())}
+        log(f"workload 8: {dt:.3f} s, CIQ {info['iters']} iterations, solve {info_s['iters']}")
     else:
         wl = workloads.workload(5)
         p = wl.problems[0]
@@ -252,11 +281,12 @@ def main() -> int:
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
-    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5, 6, 7], default=2,
+    ap.add_argument("--workload", type=int, choices=[2, 3, 4, 5, 6, 7, 8], default=2,
                     help="2: the metric's workload (default). 3: RBF-ARD N=100,000 d=8 S=256 per precision form; "
                          "4: 64 batched problems; 5: SVGP whitening forward + backward at M=5,000; "
                          "6: Thompson-sampling posterior covariance root at 50,000 candidates, 1,000 observations; "
-                         "7: Gibbs image-model sample, 25,600-dimensional sparse precision "
+                         "7: Gibbs image-model sample, 25,600-dimensional sparse precision; "
+                         "8: SVGP predictive pass at M=10,000 inducing points, 256 test points "
                          "(secondary measurements, one JSON line each)")
     ap.add_argument("--precond-rank", type=int, default=0,
                     help="R > 0: pivoted-Cholesky preconditioned CIQ of rank R (the output is R B with R R^T = K, "

@@ -301,6 +301,31 @@ int ciq_csr_mvm(const ciq_csr* a, int mode, const ciq_opts* o, const double* b, 
                 double* out, int ldo, ciq_info* info, hipStream_t stream);
 
 /*
+ * CIQ-whitened SVGP predictive distribution in natural parameters (Sec. 5.1,
+ * App. E). Inducing points Z (z->x, M = z->n; z->noise is the jitter of
+ * Kzz), test points x (nb of them), whitened variational distribution
+ * q(u') = N(m', S') given by its natural parameters theta = S'^{-1} m'
+ * (device, M) and Theta = -S'^{-1}/2 (device, M x M row-major, symmetric
+ * negative definite). Computes
+ *   a_x   = Kzz^{-1/2} k_Zx            (msMINRES-CIQ, o->dtype CIQ_F64/CIQ_F32)
+ *   c_x   = (-2 Theta)^{-1} a_x        (MINRES on the dense FP64 operator -2 Theta,
+ *                                       solve_max_iter / solve_tol, FP64 MFMA products)
+ *   mean[b] = theta . c_b,  var[b] = k(x_b, x_b) - a_b . a_b + a_b . c_b,
+ * i.e. the App. E quantities from which the O(M^2) natural-gradient step is
+ * assembled (d mean / d eta = a, d var / d eta = -2 mean a, d var / d H = a a^T).
+ *   x: device, nb x z->d, element type of z->x (double for CIQ_F64, else float).
+ *   mean, var: device, nb doubles; a_out: device M x nb doubles or NULL.
+ *   info: the CIQ run's report; info_solve: the dense solve's (nullable).
+ * Synchronous. Errors: CIQ_EINVAL (problem, pointers, nb < 1, solve_max_iter < 1,
+ * solve_tol < 0, and the option checks of ciq_invsqrt_mvm); CIQ_ENOTSUP for the
+ * split dtypes or o->precond_rank != 0.
+ */
+int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* theta,
+                     const double* Theta, const ciq_opts* o, int solve_max_iter, double solve_tol,
+                     double* mean, double* var, double* a_out, ciq_info* info,
+                     ciq_info* info_solve, hipStream_t stream);
+
+/*
  * Posterior covariance root for Thompson sampling (Sec. 5.2): with candidates
  * X* (cand->x, T = cand->n points) and observations X (x_obs, n_obs points)
  * under the same kernel,

@@ -249,6 +249,18 @@ struct SparseOp {
 hipError_t launch_spmv(const SparseOp& a, const double* x, int ldx, int s, double* y, int ldy, const int* done,
                        hipStream_t st);
 
+// y = alpha x (n doubles).
+hipError_t launch_scale(const double* x, double alpha, double* y, long long n, hipStream_t st);
+// SVGP predictive statistics per column b (a, c: M x nb row-major):
+// mean[b] = theta . c_b, var[b] = kxx - a_b . a_b + a_b . c_b.
+hipError_t launch_svgp_stats(const double* a, const double* c, const double* theta, int M, int nb, double kxx,
+                             double* mean, double* var, hipStream_t st);
+// Dense symmetric operator of a single-shift solve (SVGP: -2 Theta).
+struct DenseOp {
+    const double* A;         // n x n, row-major
+    int n;
+};
+
 // Preconditioned Lanczos direction: y <- (y - beta_j z_prev) - alpha_j z_cur
 // (alpha_j from colsum[0..ncol)), in place.
 hipError_t launch_pc_w(const Dev& d, double* y, const double* zc, const double* zp, hipStream_t st);

@@ -458,6 +458,7 @@ struct Run {
     const Precond* pc = nullptr;
     const Posterior* post = nullptr;   // products with a posterior covariance (single problem)
     const SparseOp* sp = nullptr;      // products with a caller's sparse operator (single problem, FP64)
+    const DenseOp* dn = nullptr;       // products with a dense operator (single-shift solves, FP64)
     // device memory: points in FP64, every msMINRES vector in FP64
     // (FP32 Lanczos vectors cost ~eps32 * kappa accuracy; the FP32 product only
     // consumes an FP32 copy q32 of the current Lanczos vector)
@@ -559,7 +560,7 @@ struct Run {
         nsplit = mvm_pick_nsplit(dtype, nrb, max_n, s);
         if (cached && (max_n + 63) / 64 >= 8 && nrb * 8 >= 512)
             nsplit = 8;   // one column range per XCD (split = block index mod 8)
-        if (sp) nsplit = 1;   // the sparse product writes one partial
+        if (sp || dn) nsplit = 1;   // the sparse / dense products write one partial
         ysplit = (long long)rows_total * s;
     }
 
@@ -698,6 +699,11 @@ struct Run {
             HIPCHK(launch_spmv(*sp, qbuf[(j - 1) & 1], s, s, ypart, s, &d.st->done, st));
             return CIQ_OK;
         }
+        if (dn) {
+            HIPCHK(launch_lr_apply(0.0, nullptr, 0, dn->A, dn->n, qbuf[(j - 1) & 1], s, rows_total, dn->n, s, ypart,
+                                   s, nullptr, nullptr, &d.st->done, st));
+            return CIQ_OK;
+        }
         HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
         return CIQ_OK;
     }
@@ -818,7 +824,7 @@ struct Run {
 // product's input type; the timed launches write only the partial buffer.
 template <typename T>
 int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
-    if (r.sp) {
+    if (r.sp || r.dn) {
         r.configure(1);
         return CIQ_OK;
     }
@@ -979,19 +985,20 @@ struct ScratchLock {
 template <typename T>
 int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* const* b_ptrs, int s, int ldb,
           void* const* out_ptrs, int ldo, void* solves_out, int mode, ciq_info* infos, hipStream_t st,
-          const PostSpec* post_spec = nullptr, const SparseOp* sparse = nullptr) {
+          const PostSpec* post_spec = nullptr, const SparseOp* sparse = nullptr, const DenseOp* dense = nullptr) {
     int dev;
     STCHK(get_device(&dev));
     ScratchLock lock(dev);
     const int dtype = o->dtype;
     const int check_every = o->check_every > 0 ? o->check_every : 16;
     const int steps = o->lanczos_steps > 0 ? o->lanczos_steps : 20;
-    const bool have_bounds = o->lambda_min > 0.0 && o->lambda_max >= o->lambda_min &&
-                             std::isfinite(o->lambda_max);
+    // a dense operator means one plain solve (shift 0, weight 1): no bounds
+    const bool have_bounds = dense != nullptr || (o->lambda_min > 0.0 && o->lambda_max >= o->lambda_min &&
+                                                  std::isfinite(o->lambda_max));
     const bool profile = o->profile != 0;
 
     KCache kc;
-    if (!sparse) STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
+    if (!sparse && !dense) STCHK(kcache_acquire(o, dtype, nprob, probs, kc));
     const bool precond = o->precond_rank > 0;
     Precond pc;
     Posterior po;
@@ -1002,6 +1009,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     main.cached = (kc.ptr != nullptr);
     main.precond = precond;
     main.sp = sparse;
+    main.dn = dense;
     main.dtype = dtype;
     main.s = s;
     main.Q = o->q;
@@ -1021,6 +1029,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     bnd.cached = main.cached;
     bnd.precond = precond;
     bnd.sp = sparse;
+    bnd.dn = dense;
     bnd.plan(2);
 
     Sizer sz;
@@ -1044,7 +1053,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     bnd.fill_dev();
 
     STCHK(main.upload_tables(st));
-    if (!sparse) STCHK(setup_points(main, probs, dtype, st));
+    if (!sparse && !dense) STCHK(setup_points(main, probs, dtype, st));
     STCHK(kcache_build(main, kc, st));
     bnd.kt = main.kt;
     bnd.njs = main.njs;
@@ -1115,6 +1124,13 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     // ---- shifts / weights --------------------------------------------------
     std::vector<double> th((size_t)nprob * main.Q), wh((size_t)nprob * main.Q);
     for (int p = 0; p < nprob; ++p) {
+        if (dense) {                       // x = A^{-1} b: one shift t = 0 of weight 1
+            for (int q = 0; q < main.Q; ++q) {
+                th[(size_t)p * main.Q + q] = 0.0;
+                wh[(size_t)p * main.Q + q] = (q == 0) ? 1.0 : 0.0;
+            }
+            continue;
+        }
         const int rc = ciq_setup(lmin[p], lmax[p], main.Q, &th[(size_t)p * main.Q], &wh[(size_t)p * main.Q]);
         if (rc != CIQ_OK) return CIQ_ENUMERIC;
     }
@@ -1152,6 +1168,9 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         a.prob_done = nullptr;
         if (sparse)
             HIPCHK(launch_spmv(*sparse, main.acc, s, s, main.ypart, s, nullptr, st));
+        else if (dense)
+            HIPCHK(launch_lr_apply(0.0, nullptr, 0, dense->A, dense->n, main.acc, s, main.rows_total, dense->n, s,
+                                   main.ypart, s, nullptr, nullptr, nullptr, st));
         else
             HIPCHK(launch_mvm(dtype, a, st));
         STCHK(main.post_correct(main.acc, nullptr, st));
@@ -1596,6 +1615,105 @@ int ciq_csr_mvm(const ciq_csr* a, int mode, const ciq_opts* o, const double* b, 
     const void* bp[1] = {b};
     void* op[1] = {out};
     return solve<double>(1, &p, o, bp, s, ldb, op, ldo, nullptr, mode, info, stream, nullptr, &sp);
+}
+
+int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* theta, const double* Theta,
+                     const ciq_opts* o, int solve_max_iter, double solve_tol, double* mean, double* var,
+                     double* a_out, ciq_info* info, ciq_info* info_solve, hipStream_t stream) {
+    if (!valid_problem(z) || !o || !x || nb < 1 || !theta || !Theta || !mean || !var || !info) return CIQ_EINVAL;
+    if (solve_max_iter < 1 || !(solve_tol >= 0.0) || !std::isfinite(solve_tol)) return CIQ_EINVAL;
+    if (o->dtype != CIQ_F64 && o->dtype != CIQ_F32) return CIQ_ENOTSUP;
+    if (o->precond_rank != 0) return CIQ_ENOTSUP;
+    const int M = z->n;
+    const void* dummy_b = theta;   // shape checks only
+    STCHK(check_solve_args(z, o, dummy_b, nb, nb, mean, nb, info));
+    const int dp = pad_dims(z->d, CIQ_F64);
+    double scale[CIQ_MAX_D], ones[CIQ_MAX_D];
+    point_scale(z, o->dtype, scale);
+    int ard = 0;
+    for (int k = 0; k < CIQ_MAX_D; ++k) {
+        ones[k] = 1.0;
+        if (k >= z->d) scale[k] = 0.0;
+        else if (scale[k] != scale[0]) ard = 1;
+    }
+    const bool f32 = (o->dtype == CIQ_F32);
+    DevAlloc mem;
+    size_t off = 0;
+    double *xz = nullptr, *xx = nullptr, *kzx = nullptr, *a = nullptr, *thn = nullptr, *c = nullptr;
+    float *k32 = nullptr, *a32 = nullptr;
+    auto layout = [&](char* base) {
+        off = 0;
+        xz = carve<double>(base, off, (size_t)M * dp);
+        xx = carve<double>(base, off, (size_t)nb * dp);
+        kzx = carve<double>(base, off, (size_t)M * nb);
+        a = carve<double>(base, off, (size_t)M * nb);
+        c = carve<double>(base, off, (size_t)M * nb);
+        thn = carve<double>(base, off, (size_t)M * M);
+        if (f32) {
+            k32 = carve<float>(base, off, (size_t)M * nb);
+            a32 = carve<float>(base, off, (size_t)M * nb);
+        }
+    };
+    layout(nullptr);
+    if (hipMalloc(&mem.p, off) != hipSuccess) {
+        (void)hipGetLastError();
+        mem.p = nullptr;
+        return CIQ_ENOMEM;
+    }
+    layout(static_cast<char*>(mem.p));
+    hipError_t e;
+    if (f32) {
+        e = launch_prep<float>(static_cast<const float*>(z->x), M, z->d, dp, ones, xz, stream);
+        if (e == hipSuccess) e = launch_prep<float>(static_cast<const float*>(x), nb, z->d, dp, ones, xx, stream);
+    } else {
+        e = launch_prep<double>(static_cast<const double*>(z->x), M, z->d, dp, ones, xz, stream);
+        if (e == hipSuccess) e = launch_prep<double>(static_cast<const double*>(x), nb, z->d, dp, ones, xx, stream);
+    }
+    if (e != hipSuccess) return CIQ_EHIP;
+    HIPCHK(launch_xkernel(xz, M, xx, nb, dp, z->kernel, ard, scale, z->outputscale, kzx, nb, stream));
+    // a = Kzz^{-1/2} K_Zx by msMINRES-CIQ (Kzz with its jitter z->noise)
+    if (f32) {
+        HIPCHK((launch_copy<double, float>(kzx, nb, M, nb, k32, nb, stream)));
+        const void* bp[1] = {k32};
+        void* op[1] = {a32};
+        STCHK(solve<float>(1, z, o, bp, nb, nb, op, nb, nullptr, CIQ_INVSQRT, info, stream));
+        HIPCHK((launch_copy<float, double>(a32, nb, M, nb, a, nb, stream)));
+    } else {
+        const void* bp[1] = {kzx};
+        void* op[1] = {a};
+        STCHK(solve<double>(1, z, o, bp, nb, nb, op, nb, nullptr, CIQ_INVSQRT, info, stream));
+    }
+    // c = (-2 Theta)^{-1} a: MINRES on the dense operator (one shift 0, weight 1)
+    HIPCHK(launch_scale(Theta, -2.0, thn, (long long)M * M, stream));
+    ciq_opts so{};
+    so.dtype = CIQ_F64;
+    so.q = 1;
+    so.max_iter = solve_max_iter;
+    so.tol = solve_tol;
+    so.check_every = o->check_every;
+    const double one = 1.0;
+    ciq_problem dp_{};
+    dp_.n = M;
+    dp_.d = 1;
+    dp_.x = thn;             // never read: the dense operator replaces the kernel product
+    dp_.kernel = CIQ_KERNEL_RBF;
+    dp_.n_lengthscale = 1;
+    dp_.lengthscale = &one;
+    dp_.outputscale = 1.0;
+    dp_.noise = 0.0;
+    const DenseOp dop{thn, M};
+    ciq_info si{};
+    {
+        const void* bp[1] = {a};
+        void* op[1] = {c};
+        STCHK(solve<double>(1, &dp_, &so, bp, nb, nb, op, nb, nullptr, CIQ_INVSQRT, &si, stream, nullptr, nullptr,
+                            &dop));
+    }
+    if (info_solve) *info_solve = si;
+    HIPCHK(launch_svgp_stats(a, c, theta, M, nb, z->outputscale, mean, var, stream));
+    if (a_out) HIPCHK(hipMemcpyAsync(a_out, a, (size_t)M * nb * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return CIQ_OK;
 }
 
 int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out, int* piv_out,

@@ -402,6 +402,45 @@ __global__ __launch_bounds__(256) void xkernel_kernel(const double* __restrict__
     out[(long long)i * ldo + j] = o2 * mfma::kentry64<KERNEL>(r2);
 }
 
+// y = alpha x (n doubles).
+__global__ void scale_kernel(const double* __restrict__ x, double alpha, double* __restrict__ y, long long n) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) y[e] = alpha * x[e];
+}
+
+// Per column b of the M x nb arrays a, c (row-major): mean[b] = theta . c_b,
+// var[b] = kxx - a_b . a_b + a_b . c_b; one block per column, fixed-order
+// tree reduction.
+__global__ __launch_bounds__(256) void svgp_stats_kernel(const double* __restrict__ a, const double* __restrict__ c,
+                                                         const double* __restrict__ theta, int M, int nb, double kxx,
+                                                         double* __restrict__ mean, double* __restrict__ var) {
+    __shared__ double s1[256], s2[256], s3[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    double aa = 0.0, ac = 0.0, tc = 0.0;
+    for (int i = t; i < M; i += 256) {
+        const double av = a[(long long)i * nb + b], cv = c[(long long)i * nb + b];
+        aa = fma(av, av, aa);
+        ac = fma(av, cv, ac);
+        tc = fma(theta[i], cv, tc);
+    }
+    s1[t] = aa;
+    s2[t] = ac;
+    s3[t] = tc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            s1[t] += s1[t + w];
+            s2[t] += s2[t + w];
+            s3[t] += s3[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        mean[b] = s3[0];
+        var[b] = kxx - s1[0] + s2[0];
+    }
+}
+
 // Single-problem runs only (the preconditioned path is not batched).
 __global__ void pc_w_kernel(Dev d, double* __restrict__ y, const double* __restrict__ zc,
                             const double* __restrict__ zp) {
@@ -494,6 +533,17 @@ hipError_t launch_xkernel(const double* xa, int na, const double* xb, int nb, in
         if (ard) hipLaunchKernelGGL((xkernel_kernel<CIQ_KERNEL_MATERN52, true>), g, b, 0, st, xa, na, xb, nb, dp, sc, o2, out, ldo);
         else hipLaunchKernelGGL((xkernel_kernel<CIQ_KERNEL_MATERN52, false>), g, b, 0, st, xa, na, xb, nb, dp, sc, o2, out, ldo);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* x, double alpha, double* y, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, alpha, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_svgp_stats(const double* a, const double* c, const double* theta, int M, int nb, double kxx,
+                             double* mean, double* var, hipStream_t st) {
+    hipLaunchKernelGGL(svgp_stats_kernel, dim3(nb), dim3(256), 0, st, a, c, theta, M, nb, kxx, mean, var);
     return hipGetLastError();
 }
 

@@ -216,6 +216,34 @@ def ciq_csr_mvm(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor,
     return out.reshape(b.shape), info.as_dict()
 
 
+def ciq_svgp_predict(inducing: Problem, x: torch.Tensor, theta: torch.Tensor, Theta: torch.Tensor, q: int = 15,
+                     max_iter: int = 200, tol: float = 1e-4, precision: Optional[str] = None, bounds=None,
+                     solve_max_iter: int = 1000, solve_tol: float = 1e-8, want_a: bool = False,
+                     kernel_cache: str = "auto", seed: int = 0):
+    """Whitened SVGP predictive mean and variance at x from natural parameters
+    (theta, Theta) -> (mean, var, a or None, info, info_solve)."""
+    lib = L.load()
+    code = _dtype_code(inducing.x, precision)
+    if not (x.is_cuda and x.dim() == 2 and x.is_contiguous() and x.dtype == inducing.x.dtype):
+        raise ValueError("x must be a contiguous 2-D device tensor of the inducing points' dtype")
+    M, nb = inducing.x.shape[0], x.shape[0]
+    th = theta.to(torch.float64).contiguous()
+    Th = Theta.to(torch.float64).contiguous()
+    mean = torch.empty(nb, dtype=torch.float64, device=x.device)
+    var = torch.empty(nb, dtype=torch.float64, device=x.device)
+    a = torch.empty((M, nb), dtype=torch.float64, device=x.device) if want_a else None
+    p, keep = inducing.c_struct()
+    o = _opts(code, q, max_iter, tol, 0, seed, bounds, 0, False, kernel_cache)
+    info, info_s = L.ciq_info(), L.ciq_info()
+    L.check(lib.ciq_svgp_predict(ctypes.byref(p), ctypes.c_void_p(x.data_ptr()), nb, ctypes.c_void_p(th.data_ptr()),
+                                 ctypes.c_void_p(Th.data_ptr()), ctypes.byref(o), int(solve_max_iter),
+                                 float(solve_tol), ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(var.data_ptr()),
+                                 ctypes.c_void_p(a.data_ptr()) if a is not None else None, ctypes.byref(info),
+                                 ctypes.byref(info_s), _stream()), "ciq_svgp_predict")
+    del keep
+    return mean, var, a, info.as_dict(), info_s.as_dict()
+
+
 def ciq_pivoted_cholesky(problem: Problem, rank: int):
     """Rank-`rank` partial pivoted Cholesky factor of outputscale * k(X, X):
     (Lbar as an n x rank float64 device tensor, pivots (numpy, -1 after a

@@ -231,6 +231,24 @@ def test_csr_arguments_rejected(lib):
                            None) == L.CIQ_ENOTSUP
 
 
+def test_svgp_arguments_rejected(lib):
+    p, keep = _bad_problem()
+    fake = ctypes.c_void_p(512)
+    info = L.ciq_info()
+    o = L.ciq_opts(dtype=L.CIQ_F64, q=8, max_iter=10, tol=1e-4)
+    good = dict(x=fake, nb=4, theta=fake, Theta=fake, it=10, tol=1e-8, mean=fake, var=fake)
+    for bad in [dict(x=None), dict(nb=0), dict(theta=None), dict(Theta=None), dict(it=0), dict(tol=-1.0),
+                dict(mean=None), dict(var=None)]:
+        a = {**good, **bad}
+        assert lib.ciq_svgp_predict(ctypes.byref(p), a["x"], a["nb"], a["theta"], a["Theta"], ctypes.byref(o),
+                                    a["it"], a["tol"], a["mean"], a["var"], None, ctypes.byref(info), None,
+                                    None) == L.CIQ_EINVAL, bad
+    o.dtype = L.CIQ_BF16X3
+    assert lib.ciq_svgp_predict(ctypes.byref(p), fake, 4, fake, fake, ctypes.byref(o), 10, 1e-8, fake, fake, None,
+                                ctypes.byref(info), None, None) == L.CIQ_ENOTSUP
+    del keep
+
+
 def test_strerror(lib):
     for code in range(6):
         assert lib.ciq_strerror(code)
