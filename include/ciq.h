@@ -15,7 +15,11 @@
  * regenerate K's entries from X, or stream a copy of K that the call writes
  * once and frees (ciq_opts.kernel_cache). An optional pivoted-Cholesky
  * preconditioner (Sec. 3.4, Appendix D; ciq_opts.precond_rank) gives results
- * equal to K^{+-1/2} B up to an orthogonal rotation in fewer iterations.
+ * equal to K^{+-1/2} B up to an orthogonal rotation in fewer iterations. The
+ * same engine serves the paper's applications: posterior covariance roots
+ * for Thompson sampling (ciq_posterior_mvm, Sec. 5.2), sparse operators such
+ * as a Gibbs sampler's precision (ciq_csr_mvm, Sec. 5.3) and the whitened
+ * SVGP predictive pass (ciq_svgp_predict, Sec. 5.1, App. E).
  *
  * Conventions shared by every entry point:
  *  - Status: every call returns CIQ_OK (0) or one of the CIQ_E* codes below;
