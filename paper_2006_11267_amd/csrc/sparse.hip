@@ -10,7 +10,7 @@ namespace ciq {
 
 namespace {
 
-// y[i][c] = sum_k val[k] x[col[k]][c] over row i's entries. Block: TS columns
+// y[i][c] = sum_k val[k] x[col[k]][c] over row i's entries (s > 1). Block: TS columns
 // x RL rows (TS = the power of two >= s, at most 64); each thread one (row,
 // column), entries in storage order (deterministic).
 __global__ __launch_bounds__(256) void spmv_kernel(SparseOp a, const double* __restrict__ x, int ldx, int s,
@@ -26,10 +26,32 @@ __global__ __launch_bounds__(256) void spmv_kernel(SparseOp a, const double* __r
     y[(long long)row * ldy + c] = acc;
 }
 
+// One column (s = 1): 16 lanes per row, lane g takes the row's entries
+// g, g + 16, ... (coalesced loads of val and col across the 16 lanes), the
+// 16 partial sums are combined by a fixed butterfly (deterministic).
+__global__ __launch_bounds__(256) void spmv1_kernel(SparseOp a, const double* __restrict__ x,
+                                                    double* __restrict__ y, const int* done) {
+    if (done != nullptr && *done) return;
+    const int g = threadIdx.x & 15;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    double acc = 0.0;
+    if (row < a.n) {
+        const int k1 = a.row_ptr[row + 1];
+        for (int k = a.row_ptr[row] + g; k < k1; k += 16) acc = fma(a.val[k], x[a.col[k]], acc);
+    }
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 16);
+    if (row < a.n && g == 0) y[row] = acc;
+}
+
 }  // namespace
 
 hipError_t launch_spmv(const SparseOp& a, const double* x, int ldx, int s, double* y, int ldy, const int* done,
                        hipStream_t st) {
+    if (s == 1 && ldx == 1 && ldy == 1) {
+        hipLaunchKernelGGL(spmv1_kernel, dim3((a.n + 15) / 16), dim3(256), 0, st, a, x, y, done);
+        return hipGetLastError();
+    }
     int TS = 1;
     while (TS < s && TS < 64) TS <<= 1;
     const int RL = 256 / TS;

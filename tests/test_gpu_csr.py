@@ -20,10 +20,12 @@ def _rhs(n, s, seed):
     return np.random.default_rng(seed).standard_normal((n, s))
 
 
+@pytest.mark.parametrize("s", [1, 5])
 @pytest.mark.parametrize("J", [1, 5])
 @pytest.mark.parametrize("mode", ["invsqrt", "sqrt"])
-def test_csr_small_j_parity(mode, J):
-    """24 x 24 image (576 unknowns), S = 5, same bounds, fixed J: agreement to
+def test_csr_small_j_parity(mode, J, s):
+    """24 x 24 image (576 unknowns), one column (16 lanes per row product) and
+    five (one thread per row and column), same bounds, fixed J: agreement to
     rounding (bar: 10x the oracle's move under one-ulp perturbations of the
     stored values)."""
     torch = torch_cuda()
@@ -31,8 +33,8 @@ def test_csr_small_j_parity(mode, J):
     A = gibbs.gibbs_precision(24, 1.0, 0.01)
     lam = np.linalg.eigvalsh(A.toarray())
     bounds = (lam[0], lam[-1])
-    b = _rhs(A.shape[0], 5, 3)
-    announce(f"csr small-J parity {mode} J={J}")
+    b = _rhs(A.shape[0], s, 3)
+    announce(f"csr small-J parity {mode} J={J} s={s}")
     out, info = ciq.ciq_csr_mvm(*_device_csr(torch, A), torch.from_numpy(b).cuda(), mode=mode, q=10, max_iter=J,
                                 tol=0.0, bounds=bounds)
     ref, _ = oc.ciq(lambda v: A @ v, b, bounds[0], bounds[1], 10, J, 0.0, mode)
