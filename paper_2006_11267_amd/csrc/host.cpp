@@ -1622,6 +1622,7 @@ int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* 
                      double* a_out, ciq_info* info, ciq_info* info_solve, hipStream_t stream) {
     if (!valid_problem(z) || !o || !x || nb < 1 || !theta || !Theta || !mean || !var || !info) return CIQ_EINVAL;
     if (solve_max_iter < 1 || !(solve_tol >= 0.0) || !std::isfinite(solve_tol)) return CIQ_EINVAL;
+    if (!valid_dtype(o->dtype)) return CIQ_EINVAL;
     if (o->dtype != CIQ_F64 && o->dtype != CIQ_F32) return CIQ_ENOTSUP;
     if (o->precond_rank != 0) return CIQ_ENOTSUP;
     const int M = z->n;

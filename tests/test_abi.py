@@ -246,6 +246,9 @@ def test_svgp_arguments_rejected(lib):
     o.dtype = L.CIQ_BF16X3
     assert lib.ciq_svgp_predict(ctypes.byref(p), fake, 4, fake, fake, ctypes.byref(o), 10, 1e-8, fake, fake, None,
                                 ctypes.byref(info), None, None) == L.CIQ_ENOTSUP
+    o.dtype = 9
+    assert lib.ciq_svgp_predict(ctypes.byref(p), fake, 4, fake, fake, ctypes.byref(o), 10, 1e-8, fake, fake, None,
+                                ctypes.byref(info), None, None) == L.CIQ_EINVAL
     del keep
 
 
