@@ -271,9 +271,10 @@ __global__ __launch_bounds__(256) void lr_reduce_kernel(const double* __restrict
 
 // apply: the block owns 64 rows x 64 s; wave w rows i0 + 16 w against four
 // s-tiles. MFMA (i, k, j) = (row, r, s): A-operand A[row][r] (each lane walks
-// its row 4 r at a time), B-operand T[r][s] (small, L2-resident). Operands of
-// the next group of four k-steps are loaded while the current group runs.
-constexpr int kApplyGroup = 4;
+// its row, loaded into registers one slab ahead), B-operand T[r][s] from
+// double-buffered LDS slabs of 32 r shared by the four waves (T is read once
+// per block instead of once per wave).
+constexpr int kApplySlab = 32;
 __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const double* X, int ldx,
                                                        const double* __restrict__ A, int lda,
                                                        const double* __restrict__ T, int ldt, int n, int R, int S,
@@ -281,6 +282,7 @@ __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const doub
                                                        const int* __restrict__ colmask, const int* done,
                                                        int accumulate) {
     if (done != nullptr && *done) return;
+    __shared__ double Ts[2][kApplySlab][80];
     __shared__ double red[16][64];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
@@ -288,39 +290,58 @@ __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const doub
     const int ia = i0 + wave * 16 + lr;           // this lane's A-operand row
     const bool ia_ok = ia < n;
     const double* arow = A + (long long)(ia_ok ? ia : 0) * lda;
-    bool sc_ok[4];
-#pragma unroll
-    for (int sb = 0; sb < 4; ++sb) sc_ok[sb] = s0 + sb * 16 + lr < S;
     pdx4 acc[4];
 #pragma unroll
     for (int sb = 0; sb < 4; ++sb) acc[sb] = pdx4{0.0, 0.0, 0.0, 0.0};
-    double ga[kApplyGroup], gt[kApplyGroup][4];
-    auto load = [&](int rb) {
+    constexpr int G = kApplySlab / 4;             // k-steps per slab
+    double ga[G], tn[8];
+    auto load_a = [&](int rb, double* dst) {
 #pragma unroll
-        for (int g = 0; g < kApplyGroup; ++g) {
+        for (int g = 0; g < G; ++g) {
             const int r = rb + 4 * g + lk;
-            const bool rok = r < R;
-            ga[g] = (ia_ok && rok) ? arow[r] : 0.0;
-            const double* tr = T + (long long)r * ldt + s0 + lr;
-#pragma unroll
-            for (int sb = 0; sb < 4; ++sb) gt[g][sb] = (rok && sc_ok[sb]) ? tr[16 * sb] : 0.0;
+            dst[g] = (ia_ok && r < R) ? arow[r] : 0.0;
         }
     };
-    load(0);
-    for (int rb = 0; rb < R; rb += 4 * kApplyGroup) {
-        double ca[kApplyGroup], ct[kApplyGroup][4];
+    auto load_t = [&](int rb) {
 #pragma unroll
-        for (int g = 0; g < kApplyGroup; ++g) {
-            ca[g] = ga[g];
-#pragma unroll
-            for (int sb = 0; sb < 4; ++sb) ct[g][sb] = gt[g][sb];
+        for (int k = 0; k < 8; ++k) {
+            const int e = tid + 256 * k, rr = e >> 6, cc = e & 63;
+            const int r = rb + rr, c = s0 + cc;
+            tn[k] = (r < R && c < S) ? T[(long long)r * ldt + c] : 0.0;
         }
-        if (rb + 4 * kApplyGroup < R) load(rb + 4 * kApplyGroup);
+    };
+    auto store_t = [&](int buf) {
 #pragma unroll
-        for (int g = 0; g < kApplyGroup; ++g)
+        for (int k = 0; k < 8; ++k) {
+            const int e = tid + 256 * k;
+            Ts[buf][e >> 6][e & 63] = tn[k];
+        }
+    };
+    const int nslab = (R + kApplySlab - 1) / kApplySlab;
+    load_t(0);
+    store_t(0);
+    load_a(0, ga);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        const int cur = sl & 1;
+        double gn[G];
+        const bool more = sl + 1 < nslab;
+        if (more) {
+            load_t((sl + 1) * kApplySlab);
+            load_a((sl + 1) * kApplySlab, gn);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int sb = 0; sb < 4; ++sb)
-                acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[g], ct[g][sb], acc[sb], 0, 0, 0);
+                acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[g], Ts[cur][4 * g + lk][sb * 16 + lr], acc[sb], 0,
+                                                               0, 0);
+        if (more) {
+            store_t(cur ^ 1);
+#pragma unroll
+            for (int g = 0; g < G; ++g) ga[g] = gn[g];
+        }
+        __syncthreads();
     }
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
