@@ -172,60 +172,85 @@ typedef double pdx4 __attribute__((ext_vector_type(4)));
 // part: the block owns 128 r x 64 s of one row chunk; wave w the r-tiles
 // r0 + 32 w + {0, 16} against four 16-column s-tiles (8 accumulators).
 // MFMA (i, k, j) = (r, row, s): A-operand A[row][r] (16 consecutive r per
-// row), B-operand X[row][s]. Operands of the next group of four k-steps are
-// loaded into registers while the current group's 32 MFMAs run.
-constexpr int kPartGroup = 4;
+// row, loaded into registers one group of four k-steps ahead), B-operand
+// X[row][s] from double-buffered LDS tiles of 16 rows shared by the four
+// waves (X is read once per block instead of once per wave).
+constexpr int kPartRows = 16;
 __global__ __launch_bounds__(256) void lr_part_kernel(const double* __restrict__ A, int lda,
                                                       const double* __restrict__ X, int ldx, int n, int R, int S,
                                                       int rows_per_chunk, double* __restrict__ part,
                                                       const int* done) {
     if (done != nullptr && *done) return;
-    const int chunk = blockIdx.x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    __shared__ double Xs[2][kPartRows][80];
+    const int chunk = blockIdx.x, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int r0 = blockIdx.y * 128 + wave * 32, s0 = blockIdx.z * 64;
     const int i0 = chunk * rows_per_chunk;
     const int i1 = min(n, i0 + rows_per_chunk);
     const bool ra_ok[2] = {r0 + lr < R, r0 + 16 + lr < R};
-    bool sc_ok[4];
-#pragma unroll
-    for (int sb = 0; sb < 4; ++sb) sc_ok[sb] = s0 + sb * 16 + lr < S;
     pdx4 acc[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) acc[t][sb] = pdx4{0.0, 0.0, 0.0, 0.0};
-    double ga[kPartGroup][2], gx[kPartGroup][4];
-    auto load = [&](int ib) {
+    double ga[4][2], xn[4];
+    auto load_a = [&](int ib, double (&dst)[4][2]) {
 #pragma unroll
-        for (int g = 0; g < kPartGroup; ++g) {
+        for (int g = 0; g < 4; ++g) {
             const int i = ib + 4 * g + lk;
             const bool iok = i < i1;
             const double* ar = A + (long long)i * lda + r0 + lr;
-            const double* xr = X + (long long)i * ldx + s0 + lr;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) ga[g][t] = (iok && ra_ok[t]) ? ar[16 * t] : 0.0;
-#pragma unroll
-            for (int sb = 0; sb < 4; ++sb) gx[g][sb] = (iok && sc_ok[sb]) ? xr[16 * sb] : 0.0;
+            for (int t = 0; t < 2; ++t) dst[g][t] = (iok && ra_ok[t]) ? ar[16 * t] : 0.0;
         }
     };
-    if (i0 < i1) load(i0);
-    for (int ib = i0; ib < i1; ib += 4 * kPartGroup) {
-        double ca[kPartGroup][2], cx[kPartGroup][4];
+    auto load_x = [&](int ib) {
 #pragma unroll
-        for (int g = 0; g < kPartGroup; ++g) {
-            ca[g][0] = ga[g][0];
-            ca[g][1] = ga[g][1];
-#pragma unroll
-            for (int sb = 0; sb < 4; ++sb) cx[g][sb] = gx[g][sb];
+        for (int k = 0; k < 4; ++k) {
+            const int e = tid + 256 * k, row = e >> 6, cc = e & 63;
+            const int i = ib + row, c = s0 + cc;
+            xn[k] = (i < i1 && c < S) ? X[(long long)i * ldx + c] : 0.0;
         }
-        if (ib + 4 * kPartGroup < i1) load(ib + 4 * kPartGroup);
+    };
+    auto store_x = [&](int buf) {
 #pragma unroll
-        for (int g = 0; g < kPartGroup; ++g)
+        for (int k = 0; k < 4; ++k) {
+            const int e = tid + 256 * k;
+            Xs[buf][e >> 6][e & 63] = xn[k];
+        }
+    };
+    if (i0 < i1) {
+        load_x(i0);
+        store_x(0);
+        load_a(i0, ga);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int ib = i0; ib < i1; ib += kPartRows) {
+        const bool more = ib + kPartRows < i1;
+        double gn[4][2];
+        if (more) {
+            load_x(ib + kPartRows);
+            load_a(ib + kPartRows, gn);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int sb = 0; sb < 4; ++sb)
-                    acc[t][sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[g][t], cx[g][sb], acc[t][sb], 0, 0, 0);
+                    acc[t][sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[g][t], Xs[cur][4 * g + lk][sb * 16 + lr],
+                                                                      acc[t][sb], 0, 0, 0);
+        if (more) {
+            store_x(cur ^ 1);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                ga[g][0] = gn[g][0];
+                ga[g][1] = gn[g][1];
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
