@@ -526,9 +526,11 @@ hipError_t launch_pchol_col(const PcholArgs& a, int m, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Row chunks per (r, s) tile: at most 1024 blocks in all (four per CU), so
+// that no CU holds a fifth block that would set the launch's duration.
 int lr_part_chunks(int n, int R, int S) {
     const int tiles = ((R + 127) / 128) * ((S + 63) / 64);
-    int nchunk = (1024 + tiles - 1) / tiles;
+    int nchunk = 1024 / tiles;
     nchunk = std::min(nchunk, (n + 63) / 64);
     return std::max(nchunk, 1);
 }
