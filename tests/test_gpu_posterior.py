@@ -29,7 +29,7 @@ def test_posterior_small_j_parity_fp64(mode, J, cache):
     difference of)."""
     torch = torch_cuda()
     ciq = ciq_module()
-    t, n, d, s = 1500, 121, 4, 7                     # odd n: 8-byte operand loads
+    t, n, d, s = 1500, 121, 4, 7                     # odd n: odd leading dimension of W
     kind, ls, o2, jit, s2 = "matern52", [0.35], 1.0, 1e-3, 1e-3
     xs, xo, b = _inputs(t, n, d, s, 11)
     S = opost.posterior_covariance(kind, xs, xo, ls, o2, jit, s2)
