@@ -298,8 +298,12 @@ __global__ __launch_bounds__(256) void lr_reduce_kernel(const double* __restrict
 // s-tiles. MFMA (i, k, j) = (row, r, s): A-operand A[row][r] (each lane walks
 // its row, loaded into registers one slab ahead), B-operand T[r][s] from
 // double-buffered LDS slabs of 32 r shared by the four waves (T is read once
-// per block instead of once per wave).
+// per block instead of once per wave). The slabs (36 KB) are the block's
+// only LDS -- the column-sum scratch reuses them after the last slab -- so
+// four blocks fit on a CU and a 50,000-row launch (782 blocks) is resident
+// at once.
 constexpr int kApplySlab = 32;
+constexpr int kApplyLd = 72;
 __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const double* X, int ldx,
                                                        const double* __restrict__ A, int lda,
                                                        const double* __restrict__ T, int ldt, int n, int R, int S,
@@ -307,8 +311,10 @@ __global__ __launch_bounds__(256) void lr_apply_kernel(double alpha0, const doub
                                                        const int* __restrict__ colmask, const int* done,
                                                        int accumulate) {
     if (done != nullptr && *done) return;
-    __shared__ double Ts[2][kApplySlab][80];
-    __shared__ double red[16][64];
+    __shared__ double lds[2 * kApplySlab * kApplyLd];
+    static_assert(16 * 64 <= 2 * kApplySlab * kApplyLd, "column-sum scratch must fit in the slab buffers");
+    auto Ts = reinterpret_cast<double (*)[kApplySlab][kApplyLd]>(lds);
+    auto red = reinterpret_cast<double (*)[64]>(lds);   // after the slab loop only
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int i0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
