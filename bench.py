@@ -39,7 +39,7 @@ MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0
 # runs of `bench.py --counters [--precision f64]`, each scaled by the same
 # counter's reading for a plain 512 MiB device copy
 # (profiles/mvm_kt*_kernel_matern52_n50000_s64_hbm_traffic.md).
-KT_TRAFFIC_BYTES = {"f64": 2.0741e10, "f32": 1.0256e10}
+KT_TRAFFIC_BYTES = {"f64": 2.1359e10, "f32": 1.0659e10}
 METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
 
 

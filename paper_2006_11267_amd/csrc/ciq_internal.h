@@ -125,6 +125,9 @@ size_t kcache_bytes(int n, int elem_bytes);
 hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st);
 hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st);
 hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st);
+// Blocks of the resident product (FP32 or FP64 operands, nsb column blocks of
+// 16, rt row tiles per wave) that one CU holds at once; 0 if the query fails.
+int kt_blocks_per_cu(bool f32, int nsb, int rt);
 // column blocks one product launch covers: 8 x 16 for the on-the-fly FP32
 // product, 4 x 16 otherwise
 inline int product_cap(int dtype, bool cached) { return (dtype == CIQ_F32 && !cached) ? 128 : 64; }

@@ -558,8 +558,27 @@ struct Run {
         nrb = 0;
         for (int p = 0; p < nprob; ++p) nrb += (h_n[p] + rpb - 1) / rpb;
         nsplit = mvm_pick_nsplit(dtype, nrb, max_n, s);
-        if (cached && (max_n + 63) / 64 >= 8 && nrb * 8 >= 512)
-            nsplit = 8;   // one column range per XCD (split = block index mod 8)
+        if (cached && (max_n + 63) / 64 >= 16 && nrb * 8 >= 512) {
+            // m column ranges per XCD (split = block index mod 8 picks the XCD):
+            // m = 2 when it fills the last round of equal-cost blocks on the
+            // XCD's 32 CUs enough to pay for 8 more partial products (each
+            // one more N x S FP64 write and read, ~0.2 % of a product); at
+            // most 2, so the V slices an XCD streams stay within its L2
+            const int nsb = (std::min(s, product_cap(dtype, true)) + 15) / 16;
+            const int bpc = kt_blocks_per_cu(dtype == CIQ_F32, nsb, rt);
+            int m = 1;
+            if (bpc > 0) {
+                const double slots = 32.0 * bpc;
+                auto fill = [&](int mm) {
+                    const double work = (double)nrb * mm;
+                    return work / (std::ceil(work / slots) * slots) - 0.002 * 8 * (mm - 1);
+                };
+                if (fill(2) > fill(1) + 0.01) m = 2;
+            }
+            nsplit = 8 * m;
+        } else if (cached && (max_n + 63) / 64 >= 8 && nrb * 8 >= 512) {
+            nsplit = 8;   // one column range per XCD
+        }
         if (sp || dn) nsplit = 1;   // the sparse / dense products write one partial
         ysplit = (long long)rows_total * s;
     }

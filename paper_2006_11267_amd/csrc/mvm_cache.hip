@@ -474,6 +474,32 @@ hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
     }
 }
 
+template <typename K>
+static int occupancy_of(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+int kt_blocks_per_cu(bool f32, int nsb, int rt) {
+    const int k = nsb <= 1 ? 1 : (nsb <= 2 ? 2 : 4);
+    if (f32) {
+        if (rt == 1)
+            return k == 1 ? occupancy_of(mvm_kt32_kernel<1, 1, 4, 2>)
+                          : (k == 2 ? occupancy_of(mvm_kt32_kernel<2, 1, 4, 2>) : occupancy_of(mvm_kt32_kernel<4, 1, 4, 2>));
+        return k == 1 ? occupancy_of(mvm_kt32_kernel<1, 2, 4, 2>)
+                      : (k == 2 ? occupancy_of(mvm_kt32_kernel<2, 2, 4, 2>) : occupancy_of(mvm_kt32_kernel<4, 2, 4, 2>));
+    }
+    if (rt == 1)
+        return k == 1 ? occupancy_of(mvm_kt_kernel<1, 1, 4, 2>)
+                      : (k == 2 ? occupancy_of(mvm_kt_kernel<2, 1, 4, 2>) : occupancy_of(mvm_kt_kernel<4, 1, 4, 2>));
+    return k == 1 ? occupancy_of(mvm_kt_kernel<1, 2, 4, 2>)
+                  : (k == 2 ? occupancy_of(mvm_kt_kernel<2, 2, 4, 2>) : occupancy_of(mvm_kt_kernel<4, 2, 4, 2>));
+}
+
 hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st) {
     if (!kt_rows_ok(a)) return hipErrorInvalidValue;
     const int grid = a.nrb * a.nsplit;
