@@ -11,6 +11,9 @@
 #include "ciq_internal.h"
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace ciq {
 
@@ -522,6 +525,33 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
     }
 }
 
+// Blocks of update_kernel<T> with shm bytes of coefficient tile that the
+// current device holds at once (512 if the runtime cannot say), per
+// (device, tile size), cached: the launch comes once per iteration.
+template <typename T>
+static int update_resident_blocks(size_t shm) {
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 512;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, shm});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, ncu = 0;
+    int blocks = 512;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, update_kernel<T>, 256, shm) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0 &&
+        ncu > 0)
+        blocks = per_cu * ncu;
+    else
+        (void)hipGetLastError();
+    cache[{dev, shm}] = blocks;
+    return blocks;
+}
+
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur, T* qprev,
                          const T* m_prev, T* m_cur, T* acc, T* solves, float* q32, int max_n, hipStream_t st,
@@ -530,11 +560,14 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
     int TS = col_tile(d.s);
     while (TS > 1 && (size_t)d.Q * TS * per > 49152) TS >>= 1;   // coefficient tile <= 48 KB LDS
     const int RL = 256 / TS;
+    const size_t shm = (size_t)d.Q * TS * per;
+    // as many row blocks as the device holds at once with this coefficient
+    // tile (the kernel strides over the rest of the rows)
     int bx = (max_n + RL - 1) / RL;
-    if (bx > 512) bx = 512;
+    const int cap = update_resident_blocks<T>(shm);
+    if (bx > cap) bx = cap;
     if (bx < 1) bx = 1;
     dim3 grid(bx, (d.s + TS - 1) / TS, d.nprob);
-    const size_t shm = (size_t)d.Q * TS * per;
     const long long mstride = (long long)d.rows_total * d.s;
     hipLaunchKernelGGL(update_kernel<T>, grid, dim3(256), shm, st, d, y, ysplit, nsplit, qcur, qprev,
                        m_prev, m_cur, acc, solves, mstride, TS, q32, pnext);
