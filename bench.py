@@ -413,7 +413,8 @@ def main() -> int:
             "frac": achieved / peak,
             "traffic": (KT_TRAFFIC_BYTES.get(args.precision) if info["kernel_cached"] and (n, s) == (50000, 64)
                         else None),
-            "kernel": ({"f64": "mvm_kt_kernel", "f32": "mvm_kt32_kernel"}[args.precision] if info["kernel_cached"] else
+            "kernel": ({"f64": "mvm_kt_kernel", "f32": "mvm_kt32_kernel", "f16x3": "mvm_kt16_kernel"}[args.precision]
+                       if info["kernel_cached"] else
                        {"f64": "mvm_f64mfma_kernel", "f32": "mvm_f32_kernel"}.get(args.precision, "mvm_x3_kernel")),
             "avg_ms": avg_ms, "launches": mvm_n,
         },

@@ -69,8 +69,12 @@ extern "C" {
                            hi + scaled lo parts: K V ~ Kh Vh + 2^-8 (Kh Vl + Kl Vh)
                            on bf16 MFMA, FP32 accumulation (~1e-5 per product)   */
 #define CIQ_F16X3   3   /* the same split in FP16 (lo parts scaled by 2^11),
-                           ~1e-6 per product; ciq_backward and the batched call
-                           return CIQ_ENOTSUP for both split forms               */
+                           ~1e-6 per product on the fly; with a resident K
+                           (ciq_opts.kernel_cache) the FP64 entries are stored
+                           split once, hi + 2^-11 lo (4 bytes per entry), and
+                           all four part products run on FP16 MFMA (~1e-7 per
+                           product, FP32-class); ciq_backward and the batched
+                           call return CIQ_ENOTSUP for both split forms        */
 
 #define CIQ_INVSQRT 0
 #define CIQ_SQRT    1
@@ -119,16 +123,17 @@ typedef struct ciq_opts {
     int32_t check_every;       /* iterations between host convergence polls (0: auto) */
     int32_t profile;           /* 1: time every kernel-product launch of the msMINRES
                                   loop with HIP events on `stream` (ciq_info.mvm_ms) */
-    int32_t kernel_cache;      /* CIQ_CACHE_*. Single-problem CIQ_F64 / CIQ_F32 solves
-                                  (and ciq_backward) may write the unit-scale entries
-                                  k(x_i, x_j) once per call into a device buffer of
-                                  ceil(n/128)*128 x ceil(n/64)*64 doubles (CIQ_F64,
-                                  20 GB at n = 50,000) or floats (CIQ_F32, entries
-                                  evaluated in FP64 and rounded once) and stream
-                                  them in every product instead of re-evaluating
-                                  them; the buffer is allocated and freed inside
-                                  the call. The split forms and the batched call
-                                  ignore this field.                             */
+    int32_t kernel_cache;      /* CIQ_CACHE_*. Single-problem CIQ_F64 / CIQ_F32 /
+                                  CIQ_F16X3 solves (and ciq_backward) may write the
+                                  unit-scale entries k(x_i, x_j) once per call into a
+                                  device buffer of ceil(n/128)*128 x ceil(n/64)*64
+                                  doubles (CIQ_F64, 20 GB at n = 50,000), floats
+                                  (CIQ_F32, entries evaluated in FP64 and rounded
+                                  once) or FP16 hi/lo pairs (CIQ_F16X3, 4 bytes per
+                                  entry) and stream them in every product instead of
+                                  re-evaluating them; the buffer is allocated and
+                                  freed inside the call. CIQ_BF16X3 and the batched
+                                  call ignore this field.                        */
     int32_t cache_budget_mib;  /* CIQ_CACHE_AUTO: largest matrix kept, in MiB
                                   (0: half of the free device memory at the call) */
     int32_t graph;             /* 1: capture two msMINRES iterations (all their
@@ -203,6 +208,23 @@ int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double
  */
 int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ldv,
                    void* y, int ldy, hipStream_t stream);
+
+/*
+ * Y = K V by the resident-matrix product the solvers use when
+ * ciq_opts.kernel_cache keeps K in device memory (Sec. 3.2): the unit-scale
+ * entries are written once into a buffer allocated for this call, then the
+ * product kernel runs once with the launch configuration a solve of this n
+ * and s uses, and the buffer is freed. dtype: CIQ_F64 (FP64 entries, FP64
+ * MFMA), CIQ_F32 (FP64 entries rounded once to FP32, FP32 MFMA, FP64 sums
+ * across 64-column chunks), CIQ_F16X3 (FP64 entries split into FP16
+ * hi + 2^-11 lo, V split likewise after a per-column power-of-two scale,
+ * four part products on FP16 MFMA); CIQ_BF16X3 is CIQ_ENOTSUP.
+ *   v, s, ldv, y, ldy: as for ciq_kernel_mvm.
+ * Synchronous. Errors: as for ciq_kernel_mvm; CIQ_ENOMEM if the matrix does not
+ * fit; CIQ_ENOTSUP for CIQ_BF16X3.
+ */
+int ciq_kernel_mvm_resident(const ciq_problem* p, int dtype, const void* v, int s, int ldv,
+                            void* y, int ldy, hipStream_t stream);
 
 /*
  * Extreme-eigenvalue estimate of K (Appendix B.2; Alg. S2 first step): `steps`

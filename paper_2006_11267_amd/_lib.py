@@ -117,6 +117,7 @@ PROTOTYPES = {
     "ciq_strerror": (ctypes.c_char_p, [_I]),
     "ciq_setup": (_I, [_D, _D, _I, _PD, _PD]),
     "ciq_kernel_mvm": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),
+    "ciq_kernel_mvm_resident": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),
     "ciq_eig_bounds": (_I, [ctypes.POINTER(ciq_problem), _I, _I, _VP, ctypes.c_uint64, _PD, _PD, _VP]),
     "ciq_invsqrt_mvm": (_I, [ctypes.POINTER(ciq_problem), ctypes.POINTER(ciq_opts), _VP, _I, _I, _VP, _I,
                              _VP, ctypes.POINTER(ciq_info), _VP]),

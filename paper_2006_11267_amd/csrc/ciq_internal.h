@@ -45,8 +45,9 @@ struct Dev {
     int bounds_mode;        // 1: plain Lanczos (no shifts), record T
     // dots
     int dots_blocks;        // partial blocks per problem
-    int fuse_sums;          // 1: consumers sum the dots partials themselves (few
-                            // blocks; saves the two column-sum launches)
+    int fuse_sums;          // 1: consumers sum the dots partials themselves, the
+                            // whole block cooperating in a fixed order (saves the
+                            // two column-sum launches)
     double* dots;           // [nprob][dots_blocks][s][2] (alpha, beta^2 partials)
     double* colsum;         // [2][ncol]: block-summed alpha, beta^2
     // column state
@@ -67,6 +68,36 @@ struct Dev {
     ShiftCoef* coef;
     IterState* st;
 };
+
+// Tiled split-FP16 copy of an FP64 block vector (rows x s, point-major), the
+// B operand of v_mfma_f32_16x16x32_f16: element (i, c), multiplied by a power
+// of two `scale`, is stored as hi = fp16(x) and lo = fp16((x - hi) 2^11). For
+// the k-step ks = i / 32 and the column block sb = c / 16 the buffer holds 64
+// lanes x 8 halfs of hi (1 KB), then the same of lo; lane (c % 16) +
+// 16 ((i % 32) / 8), half i % 8, so lane l of one 16-byte load holds
+// B[k = 8 (l / 16) + v][c = l % 16] of that step. `nsbt` column blocks per
+// k-step; rows up to the padded width of the resident matrix, zero beyond n.
+__host__ __device__ inline size_t op16_index(int i, int c, int nsbt) {
+    const int ks = i >> 5, r = i & 31;
+    const int lane = (c & 15) + 16 * (r >> 3);
+    return ((((size_t)ks * nsbt + (c >> 4)) * 2) * 64 + lane) * 8 + (r & 7);
+}
+inline size_t op16_halfs(size_t rows_pad, int nsbt) { return rows_pad * (size_t)nsbt * 32; }
+constexpr float kOp16Scale = 256.0f;   // scale of unit-norm Lanczos vectors (entries <= 1)
+
+// Where the update / start kernels write the split FP16 copy of the next
+// product operand (p == nullptr: none).
+struct Op16 {
+    void* p;
+    int nsbt;
+    float scale;
+};
+// column blocks of 16 in a split operand buffer for s columns: 1, 2, 4 or a
+// multiple of 8, so every launch's column blocks lie inside it
+inline int op16_nsbt(int s) {
+    const int nb = (s + 15) / 16;
+    return nb <= 1 ? 1 : nb <= 2 ? 2 : nb <= 4 ? 4 : (nb + 7) / 8 * 8;
+}
 
 // Work list entry of the kernel-product kernel: (problem, row block).
 struct WorkItem {
@@ -107,6 +138,13 @@ struct MvmArgs {
     // nullptr = evaluate entries on the fly
     const void* kt;
     long long njs;           // padded columns / 4
+    // split FP16 resident matrix (CIQ_F16X3): the operand is the tiled split
+    // copy `vt` of the FP64 vector `v` (which supplies the noise term);
+    // y = o2 (K vt) * vinv (per column vcol_inv[c] when non-null)
+    const void* vt;
+    int nsbt;
+    double vinv;
+    const double* vcol_inv;
 };
 
 // Build pass of the resident kernel matrix (mvm_cache.hip).
@@ -116,8 +154,9 @@ struct KBuildArgs {
     int n, dp, kernel, ard;
     int nchunk;              // padded columns / 64
     long long njs;           // padded columns / 4
-    int f32;                 // 1: store FP32 (entries evaluated in FP64, rounded once)
-    void* kt;                // kcache_rows(n) x kcache_cols(n) doubles or floats
+    int elem;                // 0: FP64, 1: FP32 (entries evaluated in FP64, rounded
+                             // once), 2: split FP16 hi + 2^-11 lo (4 bytes per entry)
+    void* kt;                // kcache_rows(n) x kcache_cols(n) entries
 };
 size_t kcache_rows(int n);
 size_t kcache_cols(int n);
@@ -125,12 +164,15 @@ size_t kcache_bytes(int n, int elem_bytes);
 hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st);
 hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st);
 hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st);
+hipError_t launch_mvm_kt16(const MvmArgs& a, int nsb, hipStream_t st);
 // Blocks of the resident product (FP32 or FP64 operands, nsb column blocks of
 // 16, rt row tiles per wave) that one CU holds at once; 0 if the query fails.
-int kt_blocks_per_cu(bool f32, int nsb, int rt);
+int kt_blocks_per_cu(int dtype, int nsb, int rt);
 // column blocks one product launch covers: 8 x 16 for the on-the-fly FP32
-// product, 4 x 16 otherwise
-inline int product_cap(int dtype, bool cached) { return (dtype == CIQ_F32 && !cached) ? 128 : 64; }
+// product and the resident split FP16 one, 4 x 16 otherwise
+inline int product_cap(int dtype, bool cached) {
+    return ((dtype == CIQ_F32 && !cached) || (dtype == CIQ_F16X3 && cached)) ? 128 : 64;
+}
 
 // ---- launchers (kernels.hip, mvm_f32_*.hip) ---------------------------------
 hipError_t launch_mvm_f32_rbf_iso(const MvmArgs& a, int nsb, int grid_x, hipStream_t st);
@@ -172,13 +214,19 @@ hipError_t launch_scalar(const Dev& d, hipStream_t st);
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur,
                          T* qprev, const T* m_prev, T* m_cur, T* acc, T* solves, float* q32,
-                         int max_n, hipStream_t st, T* pnext = nullptr);
+                         int max_n, hipStream_t st, T* pnext = nullptr, Op16 op = Op16{nullptr, 0, 1.0f});
 
 // pvec (nullable): preconditioned start, pvec <- pvec / beta_1 too and q32
 // copies pvec instead of q.
 template <typename T>
 hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows,
-                               hipStream_t st, T* pvec = nullptr);
+                               hipStream_t st, T* pvec = nullptr, Op16 op = Op16{nullptr, 0, 1.0f});
+
+// Split FP16 operand (op16_index layout, nsbt column blocks) of the n x s FP64
+// block x (ld): per-column power-of-two scales (scale, inv: device [s]).
+hipError_t launch_op16_split(const double* x, int n, int s, int ld, double* scale, double* inv, void* vt,
+                             int nsbt, hipStream_t st);
+
 
 template <typename TI, typename TO>
 hipError_t launch_copy(const TI* src, int ld_src, int n, int s, TO* dst, int ld_dst,

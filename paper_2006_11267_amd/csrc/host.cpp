@@ -480,6 +480,12 @@ struct Run {
     double* w = nullptr;
     const void* kt = nullptr;    // resident kernel matrix (single problem) or nullptr
     long long njs = 0;
+    // split FP16 resident products (CIQ_F16X3): tiled operand copy of q_j / p_j
+    void* vt16 = nullptr;
+    int nsbt = 0;
+    float op_scale = kOp16Scale;
+    double* opsc = nullptr;      // [s] per-column scales of an arbitrary operand (final product)
+    double* opinv = nullptr;
     Dev d{};
     long long ysplit = 0;
     // host mirrors
@@ -503,7 +509,14 @@ struct Run {
         }
         acc = a.template take<double>(vec);
         if (keep_solves) solves = a.template take<double>(vec * Q);
-        if (sizeof(T) == 4) q32 = a.template take<float>(vec);
+        if (f16_resident()) {
+            nsbt = op16_nsbt(s);
+            vt16 = a.template take<_Float16>(op16_halfs(kcache_cols(max_n), nsbt));
+            opsc = a.template take<double>(s);
+            opinv = a.template take<double>(s);
+        } else if (sizeof(T) == 4) {
+            q32 = a.template take<float>(vec);
+        }
         if (precond) {
             pbuf[0] = a.template take<double>(vec);
             pbuf[1] = a.template take<double>(vec);
@@ -542,17 +555,22 @@ struct Run {
     }
 
     int rows_per_block() const { return cached ? 64 * rt : mvm_rows_per_block(dtype, s, rt); }
+    bool f16_resident() const { return dtype == CIQ_F16X3 && cached; }
 
     void configure(int rt_) {
         rt = rt_;
-        {   // ~8 rows per thread in the inner-product kernels
+        {   // ~8 rows per thread in the inner-product kernels, at most one
+            // block per CU: the consumers (phase 1, scalar stage) sum the
+            // partials of every block themselves, so no column-sum launches.
+            // The preconditioned step reads the block-summed alpha (colsum)
+            // and writes beta^2 there itself: up to 1024 blocks, summed by
+            // colsum_kernel.
             int ts = 1;
             while (ts < s && ts < 64) ts <<= 1;
             const int rows_per_pass = 256 / ts;
-            d.dots_blocks = std::min(1024, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
-            // the preconditioned step reads the block-summed alpha (colsum) and
-            // writes beta^2 there itself
-            d.fuse_sums = (d.dots_blocks <= 32 && !precond) ? 1 : 0;
+            d.dots_blocks = std::min(precond ? 1024 : 256,
+                                     std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
+            d.fuse_sums = precond ? 0 : 1;
         }
         const int rpb = rows_per_block();
         nrb = 0;
@@ -565,7 +583,7 @@ struct Run {
             // one more N x S FP64 write and read, ~0.2 % of a product); at
             // most 2, so the V slices an XCD streams stay within its L2
             const int nsb = (std::min(s, product_cap(dtype, true)) + 15) / 16;
-            const int bpc = kt_blocks_per_cu(dtype == CIQ_F32, nsb, rt);
+            const int bpc = kt_blocks_per_cu(dtype, nsb, rt);
             int m = 1;
             if (bpc > 0) {
                 const double slots = 32.0 * bpc;
@@ -657,6 +675,10 @@ struct Run {
         a.done = &d.st->done;
         a.kt = kt;
         a.njs = njs;
+        a.vt = vt16;
+        a.nsbt = nsbt;
+        a.vinv = 1.0 / (double)op_scale;
+        a.vcol_inv = nullptr;
         return a;
     }
 
@@ -664,8 +686,9 @@ struct Run {
     // or its FP32 copy.
     const void* operand(int j) const {
         if (q32) return q32;
-        return precond ? pbuf[(j - 1) & 1] : qbuf[(j - 1) & 1];
+        return precond ? pbuf[(j - 1) & 1] : qbuf[(j - 1) & 1];   // (split FP16: the noise term's)
     }
+    Op16 op16() const { return Op16{vt16, nsbt, op_scale}; }
 
     // Iteration j's kernels after the product (the buffer roles depend on the
     // parity of j only).
@@ -688,7 +711,7 @@ struct Run {
             HIPCHK(launch_lr_dotsum(pc->dotp, lr_apply_blocks(rows_total), s, d.colsum + d.ncol, done, st));
             HIPCHK(launch_scalar(d, st));
             HIPCHK(launch_update<double>(d, ypart, ysplit, 1, pcur, qprv, mprv, mcur, acc, solves, q32, max_n, st,
-                                         pnxt));
+                                         pnxt, op16()));
             return CIQ_OK;
         }
         HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));   // also reduces the splits
@@ -696,7 +719,8 @@ struct Run {
         HIPCHK(launch_dots<double>(d, ypart, ysplit, 1, qcur, qprv, 1, st));
         HIPCHK(launch_colsum(d, 1, st));
         HIPCHK(launch_scalar(d, st));
-        HIPCHK(launch_update<double>(d, ypart, ysplit, 1, qcur, qprv, mprv, mcur, acc, solves, q32, max_n, st));
+        HIPCHK(launch_update<double>(d, ypart, ysplit, 1, qcur, qprv, mprv, mcur, acc, solves, q32, max_n, st,
+                                     nullptr, op16()));
         return CIQ_OK;
     }
 
@@ -743,6 +767,8 @@ struct Run {
                 hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed, bool use_graph = false) {
         // the state is reused scratch: clear `done` before the first kernel that reads it
         HIPCHK(launch_fill<int>(reinterpret_cast<int*>(d.st), sizeof(IterState) / sizeof(int), 0, st));
+        if (vt16)      // rows past n and columns past s of the split operand stay zero
+            HIPCHK(launch_fill<int>(static_cast<int*>(vt16), op16_halfs(kcache_cols(max_n), nsbt) / 2, 0, st));
         if (precond) {
             // start z_1 = c / beta_1, p_1 = P^{-1} c / beta_1, beta_1^2 = c^T P^{-1} c
             STCHK(pc_apply(*pc, 1.0 / pc->s2, pc->fin, qbuf[0], rows_total, s, pbuf[0], pc->dotp, nullptr, nullptr,
@@ -759,7 +785,7 @@ struct Run {
         }
         if (solves) HIPCHK(launch_fill<double>(solves, (size_t)rows_total * s * Q, 0.0, st));
         HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st,
-                                           precond ? pbuf[0] : nullptr));
+                                           precond ? pbuf[0] : nullptr, op16()));
         if (use_graph && ev_pool == nullptr) {
             hipStream_t cs = nullptr;
             hipGraph_t graph = nullptr;
@@ -848,7 +874,10 @@ int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
         return CIQ_OK;
     }
     const int nsb = (std::min(r.s, product_cap(r.dtype, r.cached)) + 15) / 16;
-    if ((r.dtype == CIQ_F32 && nsb >= 8) || r.dtype == CIQ_BF16X3 || r.dtype == CIQ_F16X3) {
+    // one row tile per wave: the widest FP32 on-the-fly and split FP16 resident
+    // launches (register budget) and the on-the-fly split forms
+    if ((r.dtype == CIQ_F32 && nsb >= 8) || (r.dtype == CIQ_F16X3 && r.cached && nsb > 4) ||
+        r.dtype == CIQ_BF16X3 || (r.dtype == CIQ_F16X3 && !r.cached)) {
         r.configure(1);
         return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
     }
@@ -954,8 +983,10 @@ struct KCache {
 // Whether (and then where) a solve keeps K resident; CIQ_OK with *out = nullptr
 // means the products evaluate entries on the fly.
 int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* probs, KCache& kc) {
-    if ((dtype != CIQ_F64 && dtype != CIQ_F32) || nprob != 1 || o->kernel_cache == CIQ_CACHE_OFF) return CIQ_OK;
-    kc.elem = (dtype == CIQ_F64) ? 8 : 4;
+    if ((dtype != CIQ_F64 && dtype != CIQ_F32 && dtype != CIQ_F16X3) || nprob != 1 ||
+        o->kernel_cache == CIQ_CACHE_OFF)
+        return CIQ_OK;
+    kc.elem = (dtype == CIQ_F64) ? 8 : 4;    // FP32, or the FP16 hi + lo pair
     const size_t bytes = kcache_bytes(probs[0].n, kc.elem);
     if (o->kernel_cache != CIQ_CACHE_ON) {
         size_t fr = 0, tot = 0;
@@ -986,7 +1017,7 @@ int kcache_build(Run<T>& r, const KCache& kc, hipStream_t st) {
     ka.ard = r.ard;
     ka.nchunk = (int)(kcache_cols(ka.n) / 64);
     ka.njs = (long long)(kcache_cols(ka.n) / 4);
-    ka.f32 = (kc.elem == 4) ? 1 : 0;
+    ka.elem = (r.dtype == CIQ_F16X3) ? 2 : (kc.elem == 4 ? 1 : 0);
     ka.kt = kc.ptr;
     HIPCHK(launch_kbuild(ka, st));
     r.kt = kc.ptr;
@@ -1081,6 +1112,11 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
                        pc, st));
         main.pc = &pc;
         bnd.pc = &pc;
+        // the operand p_j = P^{-1} z_j has p_j^T z_j = 1 and P >= sigma^2 I, so
+        // |p_j| <= 1/sigma: scale it by the power of two at most 256 sigma
+        const float sc = (float)std::ldexp(1.0, (int)std::floor(std::log2(256.0 * std::sqrt(probs[0].noise))));
+        main.op_scale = sc;
+        bnd.op_scale = sc;
     }
     if (post_spec) {
         STCHK(post_build(probs[0], dtype, main.xh, main.dp, main.kernel, main.ard, main.h_scale.data(), *post_spec,
@@ -1168,6 +1204,9 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         HIPCHK((launch_copy<double, float>(main.qbuf[0], s, main.rows_total, s, main.q32, s, st)));
         STCHK(tune_rt(main, main.q32, st));
     } else {
+        if (main.vt16)   // the trial launches read the split operand: give them zeros
+            HIPCHK(launch_fill<int>(static_cast<int*>(main.vt16), op16_halfs(kcache_cols(main.max_n), main.nsbt) / 2,
+                                    0, st));
         STCHK(tune_rt(main, main.qbuf[0], st));
     }
 
@@ -1182,9 +1221,13 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
             HIPCHK((launch_copy<double, float>(main.acc, s, main.rows_total, s, main.q32, s, st)));
             operand = main.q32;
         }
+        if (main.vt16)   // the combined solution is not unit-norm: per-column scales
+            HIPCHK(launch_op16_split(main.acc, main.rows_total, s, s, main.opsc, main.opinv, main.vt16, main.nsbt,
+                                     st));
         MvmArgs a = main.mvm_args(operand, main.ypart);
         a.done = nullptr;
         a.prob_done = nullptr;
+        if (main.vt16) a.vcol_inv = main.opinv;
         if (sparse)
             HIPCHK(launch_spmv(*sparse, main.acc, s, s, main.ypart, s, nullptr, st));
         else if (dense)
@@ -1489,6 +1532,62 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     }
     if (hipFreeAsync(buf, stream) != hipSuccess) return CIQ_EHIP;
     return CIQ_OK;
+}
+
+int ciq_kernel_mvm_resident(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,
+                            hipStream_t stream) {
+    if (!valid_problem(p) || !valid_dtype(dtype) || !v || !y || s < 1 || ldv < s || ldy < s) return CIQ_EINVAL;
+    if (dtype == CIQ_BF16X3) return CIQ_ENOTSUP;
+    int dev;
+    STCHK(get_device(&dev));
+    ScratchLock lock(dev);
+    ciq_opts o{};
+    o.dtype = dtype;
+    o.kernel_cache = CIQ_CACHE_ON;
+    KCache kc;
+    STCHK(kcache_acquire(&o, dtype, 1, p, kc));
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        Run<T> r;
+        fill_problem_tables(r, p, 1, dtype);
+        r.dtype = dtype;
+        r.s = s;
+        r.Q = 0;
+        r.max_iter = 1;
+        r.cached = true;
+        r.plan(2);
+        Sizer sz;
+        r.layout(sz, true);
+        void* base = nullptr;
+        STCHK(scratch_reserve(dev, sz.off + 4096, &base));
+        Carver c(base);
+        r.layout(c, true);
+        r.fill_dev();
+        STCHK(r.upload_tables(stream));
+        STCHK(setup_points(r, p, dtype, stream));
+        STCHK(kcache_build(r, kc, stream));
+        HIPCHK((launch_copy<T, double>(static_cast<const T*>(v), ldv, p->n, s, r.qbuf[0], s, stream)));
+        const void* operand = r.qbuf[0];
+        if (r.q32) {
+            HIPCHK((launch_copy<double, float>(r.qbuf[0], s, p->n, s, r.q32, s, stream)));
+            operand = r.q32;
+        }
+        if (r.vt16) {
+            HIPCHK(launch_fill<int>(static_cast<int*>(r.vt16), op16_halfs(kcache_cols(p->n), r.nsbt) / 2, 0, stream));
+            HIPCHK(launch_op16_split(r.qbuf[0], p->n, s, s, r.opsc, r.opinv, r.vt16, r.nsbt, stream));
+        }
+        STCHK(tune_rt(r, operand, stream));
+        MvmArgs a = r.mvm_args(operand, r.ypart);
+        a.done = nullptr;
+        a.prob_done = nullptr;
+        if (r.vt16) a.vcol_inv = r.opinv;
+        HIPCHK(launch_mvm(dtype, a, stream));
+        HIPCHK(launch_reduce_splits<T>(r.ypart, r.ysplit, r.nsplit, s, p->n, s, static_cast<T*>(y), ldy, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        return CIQ_OK;
+    };
+    if (dtype == CIQ_F64) return run(double{});
+    return run(float{});
 }
 
 int ciq_eig_bounds(const ciq_problem* p, int dtype, int steps, const void* v0, uint64_t seed,

@@ -65,7 +65,12 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
         g.y = static_cast<double*>(a.y) + c0;
         const int nsb = (g.s + 15) / 16;
         hipError_t e;
-        if (dtype == CIQ_F64 && a.kt != nullptr) {
+        if (dtype == CIQ_F16X3 && a.kt != nullptr) {
+            g.v = static_cast<const double*>(a.v) + c0;
+            g.vt = static_cast<const char*>(a.vt) + (size_t)(c0 / 16) * 128 * 16;   // 128 units of 16 B per block
+            if (a.vcol_inv) g.vcol_inv = a.vcol_inv + c0;
+            e = launch_mvm_kt16(g, nsb, st);
+        } else if (dtype == CIQ_F64 && a.kt != nullptr) {
             g.v = static_cast<const double*>(a.v) + c0;
             e = launch_mvm_kt(g, nsb, st);
         } else if (dtype == CIQ_F32 && a.kt != nullptr) {
@@ -165,57 +170,105 @@ __host__ __device__ inline int col_tile(int s) {
     return ts;
 }
 
-// Column sum k of the dots partials for global column g, in the fixed order of
-// colsum_kernel (lane r of 16 sums blocks r, r + 16, ...; then the lane sums in
-// order), so the fused and separate paths give bitwise equal results.
-__device__ inline double colsum_of(const Dev& d, int k, int g) {
+// Column sum k of the dots partials for global column g, in one fixed order
+// everywhere (colsum_kernel, and the consumers when fuse_sums is set): lane r
+// of 16 sums blocks r, r + 16, ...; then the 16 lane sums are added in lane
+// order. Fused and separate column sums are therefore bitwise equal.
+// Lane sum r (of 16): partials of blocks r, r + 16, ...
+__device__ inline double colsum_lane(const Dev& d, int k, int g, int r) {
     const int p = g / d.s, c = g - p * d.s;
     const double* base = d.dots + ((long long)p * d.dots_blocks * d.s + c) * 2 + k;
     const long long stride = (long long)d.s * 2;
-    double t = 0.0;
-    for (int r = 0; r < 16; ++r) {
-        double acc = 0.0;
-        for (int b = r; b < d.dots_blocks; b += 16) acc += base[(long long)b * stride];
-        t += acc;
-    }
-    return t;
+    double acc = 0.0;
+    for (int b = r; b < d.dots_blocks; b += 16) acc += base[(long long)b * stride];
+    return acc;
 }
 
-__device__ inline double colsum_get(const Dev& d, int k, int g) {
-    return d.fuse_sums ? colsum_of(d, k, g) : d.colsum[(long long)k * d.ncol + g];
+// colsum[k * ncol + g] (the fixed order above) for every column, by the whole
+// block (nt threads, nt a multiple of 64; sh: nt doubles of LDS): 64 columns
+// x nt/64 lanes, each lane computes lane sums r, r + nt/64, ...; the 16 lane
+// sums of a column are added in order. The results are
+// read by this block after a barrier.
+__device__ void block_colsums(const Dev& d, int k, int tid, int nt, double* sh) {
+    const int lanes = nt >> 6, cl = tid & 63, ln = tid >> 6;
+    for (int g0 = 0; g0 < d.ncol; g0 += 64) {
+        const int g = g0 + cl;
+        __syncthreads();
+        for (int r = ln; r < 16; r += lanes) sh[r * 64 + cl] = (g < d.ncol) ? colsum_lane(d, k, g, r) : 0.0;
+        __syncthreads();
+        if (ln == 0 && g < d.ncol) {
+            double t = 0.0;
+            for (int r = 0; r < 16; ++r) t += sh[r * 64 + cl];
+            d.colsum[(long long)k * d.ncol + g] = t;
+        }
+    }
+    __syncthreads();
 }
+
+__device__ void scalar_stage(const Dev& d, int tid, int nt, int* active_cnt, int& any);
 
 template <typename T>
 __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit, int nsplit,
                                                    const T* q, const T* qp, int phase) {
     __shared__ double sh[256];
+    __shared__ double lsum[16 * 64];
     if (d.st->done) return;
     const int TS = col_tile(d.s), RL = 256 / TS;
     const int p = blockIdx.z;
     const int n = d.n[p], off = d.row_off[p], s = d.s;
     const int cl = threadIdx.x % TS, rl = threadIdx.x / TS;
     const int c = blockIdx.y * TS + cl;
+    double al = 0.0;
+    if (q != nullptr && phase == 1) {
+        if (d.fuse_sums) {       // alpha_j of this block's columns from the phase-0 partials
+            if (c < s)
+                for (int r = rl; r < 16; r += RL) lsum[r * TS + cl] = colsum_lane(d, 0, p * s + c, r);
+            __syncthreads();
+            if (c < s)
+                for (int r = 0; r < 16; ++r) al += lsum[r * TS + cl];
+        } else if (c < s) {
+            al = d.colsum[p * s + c];
+        }
+    }
     double acc = 0.0;
     if (c < s) {
         const int g = p * s + c;
         const double bj = (q != nullptr) ? d.beta_cur[g] : 0.0;
-        const double al = (q != nullptr && phase == 1) ? colsum_get(d, 0, g) : 0.0;
-        for (int i = blockIdx.x * RL + rl; i < n; i += gridDim.x * RL) {
-            const long long idx = (long long)(off + i) * s + c;
-            double yv = (double)y[idx];
-            for (int k = 1; k < nsplit; ++k) yv += (double)y[k * ysplit + idx];
-            if (nsplit > 1) y[idx] = (T)yv;          // the reduced product for phase 1 / update
-            if (q == nullptr) {                       // ||b||^2
-                acc = fma(yv, yv, acc);
-                continue;
+        // rows i, i + G, i + 2G, ... (G = gridDim.x * RL) in that order; four
+        // rows' loads are issued before their arithmetic (memory-level
+        // parallelism with one block per CU), the summation order unchanged
+        constexpr int U = 4;
+        const int G = gridDim.x * RL;
+        for (int i0 = blockIdx.x * RL + rl; i0 < n; i0 += U * G) {
+            double yv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * G;
+                yv[u] = 0.0;
+                if (i < n) {
+                    const long long idx = (long long)(off + i) * s + c;
+                    yv[u] = (double)y[idx];
+                    for (int k = 1; k < nsplit; ++k) yv[u] += (double)y[k * ysplit + idx];
+                }
             }
-            // the same arithmetic, in T, as the update kernel forms q_{j+1} with
-            const T vT = (T)yv - (T)bj * qp[idx];
-            if (phase == 0) {
-                acc = fma((double)q[idx], (double)vT, acc);
-            } else {
-                const double v = (double)(vT - (T)al * q[idx]);
-                acc = fma(v, v, acc);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * G;
+                if (i >= n) break;
+                const long long idx = (long long)(off + i) * s + c;
+                if (nsplit > 1) y[idx] = (T)yv[u];    // the reduced product for phase 1 / update
+                if (q == nullptr) {                   // ||b||^2
+                    acc = fma(yv[u], yv[u], acc);
+                    continue;
+                }
+                // the same arithmetic, in T, as the update kernel forms q_{j+1} with
+                const T vT = (T)yv[u] - (T)bj * qp[idx];
+                if (phase == 0) {
+                    acc = fma((double)q[idx], (double)vT, acc);
+                } else {
+                    const double v = (double)(vT - (T)al * q[idx]);
+                    acc = fma(v, v, acc);
+                }
             }
         }
     }
@@ -276,11 +329,13 @@ template hipError_t launch_dots<double>(const Dev&, double*, long long, int, con
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void scalar_init_kernel(Dev d) {
     __shared__ int any;
+    __shared__ double sh[1024];
+    if (d.fuse_sums) block_colsums(d, 1, threadIdx.x, blockDim.x, sh);
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
     const int ncol = d.ncol, Q = d.Q;
     for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
-        const double b1 = sqrt(colsum_get(d, 1, g));
+        const double b1 = sqrt(d.colsum[ncol + g]);
         const bool ok = (b1 > 0.0) && isfinite(b1);
         d.beta1[g] = ok ? b1 : 0.0;
         d.beta_cur[g] = 0.0;
@@ -325,25 +380,22 @@ hipError_t launch_scalar_init(const Dev& d, hipStream_t st) {
 //           tau = c phibar, phibar <- -s phibar
 // Stopping: shift frozen at |phibar|/||b|| <= tol; column stops when all its
 // shifts are frozen or beta_{j+1} breaks down; run stops at max_iter.
-__global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
-    __shared__ int active_cnt[1024];
-    __shared__ int any;
+// The body, run by all `nt` threads of one block (active_cnt: nprob ints and
+// `any` in that block's LDS); the caller has checked that the run is live and
+// colsum holds the column sums of both inner products.
+__device__ void scalar_stage(const Dev& d, int tid, int nt, int* active_cnt, int& any) {
     IterState* st = d.st;
-    if (st->done) {
-        if (threadIdx.x == 0) st->live = 0;
-        return;
-    }
     const int ncol = d.ncol, Q = d.Q, s = d.s;
-    for (int p = threadIdx.x; p < d.nprob; p += blockDim.x) active_cnt[p] = 0;
-    if (threadIdx.x == 0) any = 0;
+    for (int p = tid; p < d.nprob; p += nt) active_cnt[p] = 0;
+    if (tid == 0) any = 0;
     __syncthreads();
     const int iter = st->iter;
 
-    for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
+    for (int g = tid; g < ncol; g += nt) {
         if (!d.colactive[g]) continue;
         const double bj = d.beta_cur[g];
-        double al = colsum_get(d, 0, g);
-        double bn = sqrt(fmax(colsum_get(d, 1, g), 0.0));
+        double al = d.colsum[g];
+        double bn = sqrt(fmax(d.colsum[ncol + g], 0.0));
         // ||K q_j|| ~ sqrt(alpha^2 + beta_j^2 + beta_{j+1}^2) scales the breakdown test
         bool broke = !(bn > d.bd_rtol * sqrt(al * al + bj * bj + bn * bn));
         if (!isfinite(al) || !isfinite(bn)) {
@@ -363,7 +415,7 @@ __global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
     }
     __syncthreads();
 
-    for (int idx = threadIdx.x; idx < Q * ncol; idx += blockDim.x) {
+    for (int idx = tid; idx < Q * ncol; idx += nt) {
         const int g = idx % ncol, q = idx / ncol;
         ShiftCoef cf;
         cf.delta = cf.eps = cf.ginv = cf.tau = cf.tauw = 0.0;
@@ -406,7 +458,7 @@ __global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
     }
     __syncthreads();
 
-    for (int g = threadIdx.x; g < ncol; g += blockDim.x) {
+    for (int g = tid; g < ncol; g += nt) {
         if (!d.colactive[g]) {
             d.colflag[g] = 0;
             continue;
@@ -427,12 +479,27 @@ __global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
         }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < d.nprob; p += blockDim.x) d.prob_done[p] = active_cnt[p] ? 0 : 1;
-    if (threadIdx.x == 0) {
+    for (int p = tid; p < d.nprob; p += nt) d.prob_done[p] = active_cnt[p] ? 0 : 1;
+    if (tid == 0) {
         st->iter = iter + 1;
         st->live = 1;
         if (!any || iter + 1 >= d.max_iter) st->done = 1;
     }
+}
+
+__global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
+    __shared__ int active_cnt[1024];
+    __shared__ int any;
+    __shared__ double sh[1024];
+    if (d.st->done) {
+        if (threadIdx.x == 0) d.st->live = 0;
+        return;
+    }
+    if (d.fuse_sums) {      // column sums of both inner products' partials
+        block_colsums(d, 0, threadIdx.x, blockDim.x, sh);
+        block_colsums(d, 1, threadIdx.x, blockDim.x, sh);
+    }
+    scalar_stage(d, threadIdx.x, blockDim.x, active_cnt, any);
 }
 
 hipError_t launch_scalar(const Dev& d, hipStream_t st) {
@@ -450,11 +517,22 @@ hipError_t launch_scalar(const Dev& d, hipStream_t st) {
 // m_j overwrites m_{j-2}; q_{j+1} overwrites q_{j-1}.
 // Block: TS columns x RL row lanes; grid (blocks, ceil(s/TS), nprob).
 // ----------------------------------------------------------------------------
+// Element (i, c) of the split FP16 operand copy (op16_index layout), x scaled
+// by `scale` first (a power of two, so the split is of x itself).
+__device__ inline void put_op16(_Float16* vt, int nsbt, int i, int c, double x, float scale) {
+    const double xs = x * (double)scale;
+    const _Float16 hi = (_Float16)(float)xs;
+    const _Float16 lo = (_Float16)(float)((xs - (double)hi) * 2048.0);
+    const size_t k = op16_index(i, c, nsbt);
+    vt[k] = hi;
+    vt[k + 512] = lo;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long long ysplit, int nsplit,
                                                      const T* qcur, T* qprev, const T* m_prev,
                                                      T* m_cur, T* acc, T* solves, long long mstride,
-                                                     int TS, float* q32, T* pnext) {
+                                                     int TS, float* q32, T* pnext, Op16 op) {
     extern __shared__ char smem[];
     if (!d.st->live) return;
     const int RL = 256 / TS;
@@ -512,6 +590,7 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
                 const T pn = pnext[idx] * ib;
                 pnext[idx] = pn;
                 if (q32) q32[idx] = (float)pn;
+                else if (op.p) put_op16(static_cast<_Float16*>(op.p), op.nsbt, i, c, (double)pn, op.scale);
                 continue;
             }
             double ys = (double)y[idx];
@@ -521,6 +600,7 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
             const T qn = v * ib;
             qprev[idx] = qn;
             if (q32) q32[idx] = (float)qn;      // operand copy for the FP32 kernel product
+            else if (op.p) put_op16(static_cast<_Float16*>(op.p), op.nsbt, i, c, (double)qn, op.scale);
         }
     }
 }
@@ -555,7 +635,7 @@ static int update_resident_blocks(size_t shm) {
 template <typename T>
 hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit, const T* qcur, T* qprev,
                          const T* m_prev, T* m_cur, T* acc, T* solves, float* q32, int max_n, hipStream_t st,
-                         T* pnext) {
+                         T* pnext, Op16 op) {
     const size_t per = 5 * sizeof(T) + sizeof(int);   // LDS bytes per (shift, column)
     int TS = col_tile(d.s);
     while (TS > 1 && (size_t)d.Q * TS * per > 49152) TS >>= 1;   // coefficient tile <= 48 KB LDS
@@ -570,19 +650,19 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
     dim3 grid(bx, (d.s + TS - 1) / TS, d.nprob);
     const long long mstride = (long long)d.rows_total * d.s;
     hipLaunchKernelGGL(update_kernel<T>, grid, dim3(256), shm, st, d, y, ysplit, nsplit, qcur, qprev,
-                       m_prev, m_cur, acc, solves, mstride, TS, q32, pnext);
+                       m_prev, m_cur, acc, solves, mstride, TS, q32, pnext, op);
     return hipGetLastError();
 }
 template hipError_t launch_update<double>(const Dev&, const double*, long long, int, const double*, double*,
                                           const double*, double*, double*, double*, float*, int, hipStream_t,
-                                          double*);
+                                          double*, Op16);
 
 // ----------------------------------------------------------------------------
 // Start of a run: q_1 = b / ||b|| (0 for a zero column), q_0 = 0, acc = 0.
 // The caller has copied B into q and zeroed the direction/solve buffers.
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32, T* pvec) {
+__global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32, T* pvec, Op16 op) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)d.rows_total * d.s;
     if (e >= total) return;
@@ -596,8 +676,11 @@ __global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32, T
         const T pv = pvec[e] * inv;
         pvec[e] = pv;
         if (q32) q32[e] = (float)pv;
+        else if (op.p) put_op16(static_cast<_Float16*>(op.p), op.nsbt, row, c, (double)pv, op.scale);
     } else if (q32) {
         q32[e] = (float)qv;
+    } else if (op.p) {
+        put_op16(static_cast<_Float16*>(op.p), op.nsbt, row, c, (double)qv, op.scale);
     }
     qprev[e] = (T)0;
     acc[e] = (T)0;
@@ -605,14 +688,60 @@ __global__ void init_vectors_kernel(Dev d, T* q, T* qprev, T* acc, float* q32, T
 
 template <typename T>
 hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows, hipStream_t st,
-                               T* pvec) {
+                               T* pvec, Op16 op) {
     const long long total = (long long)rows * d.s;
     hipLaunchKernelGGL(init_vectors_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, d, q,
-                       qprev, acc, q32, pvec);
+                       qprev, acc, q32, pvec, op);
     return hipGetLastError();
 }
 template hipError_t launch_init_vectors<double>(const Dev&, double*, double*, double*, float*, int, hipStream_t,
-                                                double*);
+                                                double*, Op16);
+
+// ----------------------------------------------------------------------------
+// Split FP16 operand of an arbitrary FP64 block vector: per column a power of
+// two 2^e with max_i |x[i][c]| 2^e in [128, 256) (1 for a zero column), then
+// the op16 split of x[i][c] 2^e. inv[c] = 2^-e undoes it in the product.
+// Block: 64 columns x 16 row lanes, fixed combination order.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void op16_scale_kernel(const double* x, int n, int s, int ld, double* scale,
+                                                          double* inv) {
+    __shared__ double sh[1024];
+    const int cl = threadIdx.x & 63, lane = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    double m = 0.0;
+    if (c < s)
+        for (int i = lane; i < n; i += 16) m = fmax(m, fabs(x[(long long)i * ld + c]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    if (lane == 0 && c < s) {
+        for (int r = 1; r < 16; ++r) m = fmax(m, sh[r * 64 + cl]);
+        double sc = 1.0;
+        if (m > 0.0 && isfinite(m)) {
+            int e = 0;
+            (void)frexp(m, &e);          // m in [2^(e-1), 2^e)
+            sc = ldexp(1.0, 8 - e);      // m sc in [128, 256)
+        }
+        scale[c] = sc;
+        inv[c] = 1.0 / sc;
+    }
+}
+
+__global__ void op16_split_kernel(const double* x, int n, int s, int ld, const double* scale, _Float16* vt,
+                                  int nsbt) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * s) return;
+    const int i = (int)(e / s), c = (int)(e - (long long)i * s);
+    put_op16(vt, nsbt, i, c, x[(long long)i * ld + c], (float)scale[c]);
+}
+
+hipError_t launch_op16_split(const double* x, int n, int s, int ld, double* scale, double* inv, void* vt,
+                             int nsbt, hipStream_t st) {
+    hipLaunchKernelGGL(op16_scale_kernel, dim3((s + 63) / 64), dim3(1024), 0, st, x, n, s, ld, scale, inv);
+    const long long total = (long long)n * s;
+    hipLaunchKernelGGL(op16_split_kernel, dim3((int)((total + 255) / 256)), dim3(256), 0, st, x, n, s, ld, scale,
+                       static_cast<_Float16*>(vt), nsbt);
+    return hipGetLastError();
+}
 
 // ----------------------------------------------------------------------------
 // Strided copy, fill, counter-based random start vector.

@@ -25,6 +25,21 @@
 // and contracts them on v_mfma_f32_16x16x4_f32, whose A-operand lane layout
 // is the FP64 one. FP64 entries rounded once are ~10x more accurate than the
 // FP32 evaluation the on-the-fly FP32 product uses.
+//
+// The split FP16 form (CIQ_F16X3) stores every FP64 entry k as two halves,
+// hi = fp16(k) and lo = fp16((k - hi) 2^11) (4 bytes per entry, like FP32),
+// in the A-operand order of v_mfma_f32_16x16x32_f16: for the 16-row tile ib
+// and the k-step ks (32 columns), 64 lanes x 8 halfs of hi then of lo, lane l
+// holding K[16 ib + l % 16][32 ks + 8 (l / 16) + v], v = 0..7:
+//     kt16[(((ib * nks + ks) * 2 + part) * 64 + lane) * 8 + v],  nks = padded columns / 32.
+// Unit-scale entries lie in [0, 1]: hi + 2^-11 lo carries 22 significant
+// bits (absolute error <= 2^-22 |k| for normal hi, ~1e-11 below FP16's
+// normal range). The product multiplies the split operand vh + 2^-11 vl
+// (op16_index layout) by all four part pairs,
+//     K V ~ Kh Vh + 2^-11 (Kh Vl + Kl Vh) + 2^-22 Kl Vl,
+// on v_mfma_f32_16x16x32_f16 with FP32 accumulators (the hi x hi sum flushed
+// into FP64 after every 64-column chunk). Its bytes per entry equal the FP32
+// form's while its MFMA work is a fifth, so it streams K at HBM speed.
 #include "mvm_mfma.h"
 
 namespace ciq {
@@ -33,10 +48,11 @@ namespace {
 using mfma::doublex4;
 using mfma::floatx4;
 typedef double doublex2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // ---- build pass ------------------------------------------------------------
 // grid.x: 64-row blocks (one 16-row tile per wave), grid.y: column ranges.
-template <int KERNEL, int DP, bool ARD, bool F32>
+template <int KERNEL, int DP, bool ARD, int ELEM>
 __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
     constexpr int BN = 64;
     constexpr int XE = BN * DP;
@@ -73,6 +89,8 @@ __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
         return mfma::kentry64<KERNEL>(r2);
     };
     floatx4* __restrict__ out32 = reinterpret_cast<floatx4*>(static_cast<float*>(a.kt) + (size_t)tile * a.njs * 64) + lane;
+    // split FP16: a 16-row tile is njs * 16 units of 8 halfs (4 bytes per entry)
+    f16x8* __restrict__ out16 = reinterpret_cast<f16x8*>(a.kt) + (size_t)tile * a.njs * 16 + lane;
     for (int c = c0; c < c1; ++c) {
         __syncthreads();
         for (int e = tid; e < XE; e += 256) {
@@ -80,7 +98,21 @@ __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
             xs[e] = (j < n) ? a.xh[(long long)c * BN * DP + e] : 0.0;
         }
         __syncthreads();
-        if (F32) {
+        if (ELEM == 2) {
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                f16x8 hv, lv;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const double k = entry(32 * ks + 8 * (lane >> 4) + v);
+                    const _Float16 hi = (_Float16)(float)k;
+                    hv[v] = hi;
+                    lv[v] = (_Float16)(float)((k - (double)hi) * 2048.0);
+                }
+                __builtin_nontemporal_store(hv, out16 + (size_t)(c * 4 + 2 * ks) * 64);
+                __builtin_nontemporal_store(lv, out16 + (size_t)(c * 4 + 2 * ks + 1) * 64);
+            }
+        } else if (ELEM == 1) {
 #pragma unroll 2
             for (int p = 0; p < 4; ++p) {
                 floatx4 kv;
@@ -100,22 +132,23 @@ __global__ __launch_bounds__(256) void kbuild_kernel(KBuildArgs a) {
     }
 }
 
-template <int KERNEL, bool ARD, bool F32>
+template <int KERNEL, bool ARD, int ELEM>
 hipError_t launch_kbuild_dp(const KBuildArgs& a, dim3 grid, hipStream_t st) {
     switch (a.dp) {
-        case 4: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 4, ARD, F32>), grid, dim3(256), 0, st, a); break;
-        case 6: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 6, ARD, F32>), grid, dim3(256), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 8, ARD, F32>), grid, dim3(256), 0, st, a); break;
-        case 10: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 10, ARD, F32>), grid, dim3(256), 0, st, a); break;
-        case 12: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 12, ARD, F32>), grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 16, ARD, F32>), grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 4, ARD, ELEM>), grid, dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 6, ARD, ELEM>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 8, ARD, ELEM>), grid, dim3(256), 0, st, a); break;
+        case 10: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 10, ARD, ELEM>), grid, dim3(256), 0, st, a); break;
+        case 12: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 12, ARD, ELEM>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((kbuild_kernel<KERNEL, 16, ARD, ELEM>), grid, dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
 }
 
 template <int KERNEL, bool ARD>
 hipError_t launch_kbuild_t(const KBuildArgs& a, dim3 grid, hipStream_t st) {
-    return a.f32 ? launch_kbuild_dp<KERNEL, ARD, true>(a, grid, st) : launch_kbuild_dp<KERNEL, ARD, false>(a, grid, st);
+    if (a.elem == 2) return launch_kbuild_dp<KERNEL, ARD, 2>(a, grid, st);
+    return a.elem == 1 ? launch_kbuild_dp<KERNEL, ARD, 1>(a, grid, st) : launch_kbuild_dp<KERNEL, ARD, 0>(a, grid, st);
 }
 
 // ---- streaming product -----------------------------------------------------
@@ -421,6 +454,140 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
     }
 }
 
+// Split FP16 resident matrix (CIQ_F16X3): the same block structure; per
+// 64-column chunk the block stages the chunk's split V operands (NSB column
+// blocks x 2 k-steps x hi/lo, already in B-operand order) in LDS with 16-byte
+// copies, and each wave contracts its RT tiles' split K operands (four
+// 16-byte loads per lane and tile, the next chunk's in flight) with all four
+// part pairs.
+template <int NSB, int RT, int WAVES, int KD>
+__global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
+    constexpr int NT = 64 * WAVES;
+    constexpr int VU = 2 * NSB * 128;            // 16-byte V units per chunk
+    static_assert(VU % NT == 0, "V units per thread");
+    constexpr int UPT = VU / NT;
+    __shared__ f16x8 vs[VU];
+
+    if (mfma::done_now(a.done)) return;
+    const int nsplit = a.nsplit;
+    const int split = (int)(blockIdx.x % (unsigned)nsplit);
+    const int rb = (int)(blockIdx.x / (unsigned)nsplit);
+    const int n = a.n;
+    const double o2 = a.o2, s2 = a.s2;
+    const double* __restrict__ v = static_cast<const double*>(a.v);
+    const f16x8* __restrict__ vt = static_cast<const f16x8*>(a.vt);
+    const long long kstride = (long long)a.nsbt * 128;          // units per k-step
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    const int s = a.s, ldv = a.ldv, ldy = a.ldy;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tile0 = (rb * WAVES + wave) * RT;
+    const int row0 = tile0 * 16;
+
+    const int nchunk = (n + 63) / 64;
+    const int c0 = (int)(((long long)split * nchunk) / nsplit);
+    const int c1 = (int)(((long long)(split + 1) * nchunk) / nsplit);
+
+    floatx4 ah[RT][NSB], ax[RT][NSB], al[RT][NSB];
+    double accd[RT][NSB][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) {
+            ah[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ax[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            al[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
+        }
+
+    // unit u of a chunk: k-step kk = u / (NSB * 128) of the chunk, then the
+    // NSB column blocks' hi/lo units in buffer order (one contiguous span)
+    f16x8 vreg[UPT];
+    auto fetch_v = [&](int c) {
+#pragma unroll
+        for (int m = 0; m < UPT; ++m) {
+            const int u = tid + NT * m;
+            const int kk = u / (NSB * 128);
+            vreg[m] = vt[(long long)(2 * c + kk) * kstride + (u - kk * NSB * 128)];
+        }
+    };
+    const f16x8* kb[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) kb[rt] = static_cast<const f16x8*>(a.kt) + (size_t)(tile0 + rt) * a.njs * 16;
+    f16x8 kq[KD][RT][4];
+    auto fetch_k = [&](int c, f16x8 (&dst)[RT][4]) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                dst[rt][p] = __builtin_nontemporal_load(kb[rt] + (size_t)c * 256 + (unsigned)(64 * p + lane));
+    };
+    auto chunk = [&](int c, f16x8 (&cur)[RT][4], f16x8 (&far)[RT][4]) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < UPT; ++m) vs[tid + NT * m] = vreg[m];
+        __syncthreads();
+        if (c + 1 < c1) fetch_v(c + 1);
+        if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb) {
+                const f16x8 bh = vs[(kk * NSB + sb) * 128 + lane];
+                const f16x8 bl = vs[(kk * NSB + sb) * 128 + 64 + lane];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    ah[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk], bh, ah[rt][sb], 0, 0, 0);
+                    ax[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk], bl, ax[rt][sb], 0, 0, 0);
+                    ax[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk + 1], bh, ax[rt][sb], 0, 0, 0);
+                    al[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk + 1], bl, al[rt][sb], 0, 0, 0);
+                }
+            }
+        }
+        // the hi x hi sum leaves FP32 after every chunk; the cross sums are
+        // 2^-11 and 2^-22 smaller and stay in FP32 for the whole range
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int sb = 0; sb < NSB; ++sb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)ah[rt][sb][r];
+                ah[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+    if (c0 < c1) fetch_v(c0);
+#pragma unroll
+    for (int q = 0; q + 1 < KD; ++q)
+        if (c0 + q < c1) fetch_k(c0 + q, kq[q]);
+    for (int c = c0; c < c1; c += KD) {
+#pragma unroll
+        for (int q = 0; q < KD; ++q)
+            if (c + q < c1) chunk(c + q, kq[q], kq[(q + KD - 1) % KD]);
+    }
+
+    constexpr double k11 = 1.0 / 2048.0, k22 = 1.0 / 4194304.0;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int sb = 0; sb < NSB; ++sb) {
+            const int cc = sb * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;   // 16x16 accumulator layout
+                if (i < n && cc < s) {
+                    const double vi = a.vcol_inv ? a.vcol_inv[cc] : a.vinv;
+                    const double kv = accd[rt][sb][r] + ((double)ax[rt][sb][r] * k11 + (double)al[rt][sb][r] * k22);
+                    double val = o2 * kv * vi;
+                    if (split == 0) val = fma(s2, v[(long long)i * ldv + cc], val);
+                    y[(long long)i * ldy + cc] = val;
+                }
+            }
+        }
+    }
+}
+
 template <int NSB>
 hipError_t launch_kt_nsb(const MvmArgs& a, int grid, hipStream_t st) {
     if (a.rt == 1)
@@ -484,8 +651,26 @@ static int occupancy_of(K kernel) {
     return nb;
 }
 
-int kt_blocks_per_cu(bool f32, int nsb, int rt) {
+template <int NSB>
+hipError_t launch_kt16_nsb(const MvmArgs& a, int grid, hipStream_t st) {
+    if (a.rt == 1 || NSB > 4)
+        hipLaunchKernelGGL((mvm_kt16_kernel<NSB, 1, 4, 2>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((mvm_kt16_kernel<NSB, (NSB > 4 ? 1 : 2), 4, 2>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int kt_blocks_per_cu(int dtype, int nsb, int rt) {
     const int k = nsb <= 1 ? 1 : (nsb <= 2 ? 2 : 4);
+    if (dtype == CIQ_F16X3) {
+        if (nsb > 4) return occupancy_of(mvm_kt16_kernel<8, 1, 4, 2>);
+        if (rt == 1)
+            return k == 1 ? occupancy_of(mvm_kt16_kernel<1, 1, 4, 2>)
+                          : (k == 2 ? occupancy_of(mvm_kt16_kernel<2, 1, 4, 2>) : occupancy_of(mvm_kt16_kernel<4, 1, 4, 2>));
+        return k == 1 ? occupancy_of(mvm_kt16_kernel<1, 2, 4, 2>)
+                      : (k == 2 ? occupancy_of(mvm_kt16_kernel<2, 2, 4, 2>) : occupancy_of(mvm_kt16_kernel<4, 2, 4, 2>));
+    }
+    const bool f32 = (dtype == CIQ_F32);
     if (f32) {
         if (rt == 1)
             return k == 1 ? occupancy_of(mvm_kt32_kernel<1, 1, 4, 2>)
@@ -507,6 +692,21 @@ hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st) {
         case 1: return launch_kt32_nsb<1>(a, grid, st);
         case 2: return launch_kt32_nsb<2>(a, grid, st);
         default: return launch_kt32_nsb<4>(a, grid, st);
+    }
+}
+
+// a.vt points at the launch's first column block; the operand buffer spans
+// the matrix's padded columns (k-steps) and nsbt column blocks
+hipError_t launch_mvm_kt16(const MvmArgs& a, int nsb, hipStream_t st) {
+    if (!kt_rows_ok(a) || a.vt == nullptr || a.nsbt < 1) return hipErrorInvalidValue;
+    if (nsb > 4 && a.rt != 1) return hipErrorInvalidValue;
+    const int grid = a.nrb * a.nsplit;
+    switch (nsb) {
+        case 1: return launch_kt16_nsb<1>(a, grid, st);
+        case 2: return launch_kt16_nsb<2>(a, grid, st);
+        case 3:
+        case 4: return launch_kt16_nsb<4>(a, grid, st);
+        default: return launch_kt16_nsb<8>(a, grid, st);
     }
 }
 

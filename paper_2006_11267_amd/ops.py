@@ -100,6 +100,21 @@ def ciq_kernel_mvm(problem: Problem, v: torch.Tensor, precision: Optional[str] =
     return y.reshape(v.shape)
 
 
+def ciq_kernel_mvm_resident(problem: Problem, v: torch.Tensor, precision: Optional[str] = None) -> torch.Tensor:
+    """Y = K V through the solvers' resident-matrix product (K written once for
+    the call, then streamed); synchronous."""
+    lib = L.load()
+    code = _dtype_code(problem.x, precision)
+    v2 = v if v.dim() == 2 else v.reshape(-1, 1)
+    y = torch.empty(v2.shape, dtype=_elem_dtype(code), device=v.device)
+    p, keep = problem.c_struct()
+    L.check(lib.ciq_kernel_mvm_resident(ctypes.byref(p), code, ctypes.c_void_p(v2.data_ptr()), v2.shape[1],
+                                        v2.stride(0), ctypes.c_void_p(y.data_ptr()), y.stride(0), _stream()),
+            "ciq_kernel_mvm_resident")
+    del keep
+    return y.reshape(v.shape)
+
+
 def ciq_eig_bounds(problem: Problem, steps: int = 20, v0: Optional[torch.Tensor] = None, seed: int = 0,
                    precision: Optional[str] = None):
     lib = L.load()

@@ -174,8 +174,8 @@ def test_resident_matrix_small_j_parity(kind, n, s, d, ard):
 
 
 def test_kernel_cache_policy():
-    """auto keeps K only within the budget; FP64 and FP32 cache, the split
-    forms never do."""
+    """auto keeps K only within the budget; FP64, FP32 and split FP16 cache,
+    split BF16 never does."""
     torch = torch_cuda()
     ciq = ciq_module()
     rng = np.random.default_rng(5)
@@ -198,6 +198,9 @@ def test_kernel_cache_policy():
     _, ix3, _ = ciq.ciq_invsqrt_mvm(p32, bt.float(), q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
                                     kernel_cache="on", precision="bf16x3")
     assert not ix3["kernel_cached"]
+    _, i16, _ = ciq.ciq_invsqrt_mvm(p32, bt.float(), q=4, max_iter=5, tol=0.0, bounds=(0.1, 300.0),
+                                    precision="f16x3")
+    assert i16["kernel_cached"]
 
 
 @pytest.mark.parametrize("cache", ["on", "off"])
@@ -224,11 +227,13 @@ def test_fp32_matches_fp64_oracle(kind, n, s, d, cache):
         assert err < 1e-4, (mode, err, info["iters"])
 
 
-@pytest.mark.parametrize("prec,bar", [("bf16x3", 5e-3), ("f16x3", 5e-4)])
-def test_split_forms_against_exact(prec, bar):
+@pytest.mark.parametrize("prec,cache,bar", [("bf16x3", "off", 5e-3), ("f16x3", "off", 5e-4), ("f16x3", "on", 1e-4)])
+def test_split_forms_against_exact(prec, cache, bar):
     """The split-operand BF16 / FP16 products inside a full CIQ solve: the
     error against the exact K^{-1/2}B and K^{1/2}B (eigendecomposition) is
-    stated per form, bounded loosely here (kappa ~ 2e4)."""
+    stated per form, bounded loosely here (kappa ~ 2e4). With the resident
+    split FP16 matrix (22-bit entries, four part products) the bar is the
+    FP32 path's."""
     torch = torch_cuda()
     ciq = ciq_module()
     rng = np.random.default_rng(21)
@@ -242,12 +247,39 @@ def test_split_forms_against_exact(prec, bar):
     prob = ciq.Problem(torch.from_numpy(x).cuda(), "matern52", [0.3], 1.0, 1e-2)
     for mode, fn, pw in [("invsqrt", ciq.ciq_invsqrt_mvm, -0.5), ("sqrt", ciq.ciq_sqrt_mvm, 0.5)]:
         out, info, _ = fn(prob, torch.from_numpy(b).cuda(), q=15, max_iter=3000, tol=1e-7, bounds=bounds,
-                          precision=prec)
+                          precision=prec, kernel_cache=cache)
+        assert info["kernel_cached"] == (cache == "on")
         exact = ociq.exact_power(K, b.astype(np.float64), pw)
         err = colwise_rel(out.cpu().numpy(), exact).max()
         print(f"{prec} {mode}: max rel err vs exact {err:.3e}, iters {info['iters']}", flush=True)
         assert info["converged"]
         assert err < bar, (mode, err)
+
+
+@pytest.mark.parametrize("kind,n,s,d", [("matern52", 2000, 16, 6), ("rbf", 1500, 33, 8), ("rbf", 999, 64, 3),
+                                        ("matern52", 4500, 64, 6), ("rbf", 1100, 130, 4)])
+def test_f16x3_resident_matches_fp64_oracle(kind, n, s, d):
+    """The resident split FP16 form in full solves (both modes) against the
+    oracle run to 1e-10, at the FP32 path's 1e-4 bar; includes one column
+    range per XCD (n = 4500) and two column groups (s = 130)."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(n + 1)
+    x = rng.random((n, d)).astype(np.float32)
+    b = rng.standard_normal((n, s)).astype(np.float32)
+    K = okern.kernel_matrix(kind, x.astype(np.float64), [0.3], 1.0, 1e-2)
+    lam = np.linalg.eigvalsh(K)
+    bounds = (lam[0], lam[-1])
+    announce(f"ciq f16x3 resident {kind} n={n} s={s} d={d}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), kind, [0.3], 1.0, 1e-2)
+    for mode, fn in [("invsqrt", ciq.ciq_invsqrt_mvm), ("sqrt", ciq.ciq_sqrt_mvm)]:
+        out, info, _ = fn(prob, torch.from_numpy(b).cuda(), q=12, max_iter=1000, tol=1e-6, bounds=bounds,
+                          precision="f16x3", kernel_cache="on")
+        assert info["kernel_cached"]
+        ref, _ = ociq.ciq(lambda v: K @ v, b.astype(np.float64), bounds[0], bounds[1], 12, 1000, 1e-10, mode)
+        err = colwise_rel(out.cpu().numpy(), ref).max()
+        print(f"f16x3 resident {mode} {kind} n={n}: {err:.2e} ({info['iters']} iterations)", flush=True)
+        assert err < 1e-4, (mode, err, info["iters"])
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
