@@ -45,9 +45,10 @@ struct Dev {
     int bounds_mode;        // 1: plain Lanczos (no shifts), record T
     // dots
     int dots_blocks;        // partial blocks per problem
-    int fuse_sums;          // 1: consumers sum the dots partials themselves, the
-                            // whole block cooperating in a fixed order (saves the
-                            // two column-sum launches)
+    int fuse_sums;          // consumers sum the dots partials themselves, the whole
+                            // block cooperating in a fixed order: bit 1 the scalar
+                            // stage (both sums), bit 2 inner-product phase 1
+                            // (alpha); each saves a column-sum launch
     double* dots;           // [nprob][dots_blocks][s][2] (alpha, beta^2 partials)
     double* colsum;         // [2][ncol]: block-summed alpha, beta^2
     // column state

@@ -559,18 +559,16 @@ struct Run {
 
     void configure(int rt_) {
         rt = rt_;
-        {   // ~8 rows per thread in the inner-product kernels, at most one
-            // block per CU: the consumers (phase 1, scalar stage) sum the
-            // partials of every block themselves, so no column-sum launches.
-            // The preconditioned step reads the block-summed alpha (colsum)
-            // and writes beta^2 there itself: up to 1024 blocks, summed by
-            // colsum_kernel.
+        {   // ~8 rows per thread in the inner-product kernels. The scalar
+            // stage sums both inner products' block partials itself; with few
+            // blocks phase 1 sums the alpha partials itself too. The
+            // preconditioned step reads the block-summed alpha (colsum) and
+            // writes beta^2 there itself.
             int ts = 1;
             while (ts < s && ts < 64) ts <<= 1;
             const int rows_per_pass = 256 / ts;
-            d.dots_blocks = std::min(precond ? 1024 : 256,
-                                     std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
-            d.fuse_sums = precond ? 0 : 1;
+            d.dots_blocks = std::min(1024, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
+            d.fuse_sums = precond ? 0 : (d.dots_blocks <= 32 ? 3 : 1);
         }
         const int rpb = rows_per_block();
         nrb = 0;
@@ -1440,6 +1438,76 @@ int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const doubl
     return CIQ_OK;
 }
 
+// ---- on-the-fly kernel product (ciq_kernel_mvm and its allocation-free form)
+struct KmvmPlan {
+    int dp, nrb, nsplit;
+    bool direct;            // FP64 into y directly (one split, <= 64 columns)
+    size_t xbytes, ybytes;  // scaled points (256-byte rounded), FP64 split partials
+};
+
+KmvmPlan kmvm_plan(const ciq_problem* p, int dtype, int s) {
+    KmvmPlan pl{};
+    pl.dp = pad_dims(p->d, dtype);
+    const int rpb = mvm_rows_per_block(dtype, s, 2);
+    pl.nrb = (p->n + rpb - 1) / rpb;
+    pl.nsplit = mvm_pick_nsplit(dtype, pl.nrb, p->n, s);
+    pl.xbytes = ((size_t)p->n * pl.dp * sizeof(double) + 255) & ~size_t(255);
+    pl.direct = (dtype == CIQ_F64 && pl.nsplit == 1 && s <= 64);
+    pl.ybytes = pl.direct ? 0 : (size_t)pl.nsplit * p->n * s * sizeof(double);
+    return pl;
+}
+
+// Queues Y = K V on `stream` with `buf` (>= xbytes + ybytes, 256-byte aligned)
+// holding the scaled points and the split partials.
+int kmvm_run(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy, const KmvmPlan& pl,
+             void* buf, hipStream_t stream) {
+    double scale[CIQ_MAX_D];
+    point_scale(p, dtype, scale);
+    double ones[CIQ_MAX_D];
+    for (int k = 0; k < CIQ_MAX_D; ++k) ones[k] = 1.0;
+    hipError_t e;
+    if (dtype == CIQ_F64)
+        e = launch_prep<double>(static_cast<const double*>(p->x), p->n, p->d, pl.dp, ones, static_cast<double*>(buf),
+                                stream);
+    else
+        e = launch_prep<float>(static_cast<const float*>(p->x), p->n, p->d, pl.dp, ones, static_cast<double*>(buf),
+                               stream);
+    if (e != hipSuccess) return CIQ_EHIP;
+    MvmArgs a{};
+    a.xh = buf;
+    a.v = v;
+    a.y = pl.direct ? y : static_cast<void*>(static_cast<char*>(buf) + pl.xbytes);
+    a.ysplit = pl.direct ? 0 : (long long)p->n * s;
+    a.ldv = ldv;
+    a.ldy = pl.direct ? ldy : s;
+    a.s = s;
+    a.kernel = p->kernel;
+    a.dp = pl.dp;
+    a.nsplit = pl.nsplit;
+    a.rt = 2;
+    a.ard = 0;
+    for (int k = 0; k < CIQ_MAX_D; ++k) {
+        a.scale[k] = (k < p->d) ? scale[k] : 0.0;
+        if (k < p->d && scale[k] != scale[0]) a.ard = 1;
+    }
+    a.pscale = nullptr;
+    a.n = p->n;
+    a.o2 = p->outputscale;
+    a.s2 = p->noise;
+    a.nrb = pl.nrb;
+    if (launch_mvm(dtype, a, stream) != hipSuccess) return CIQ_EHIP;
+    if (!pl.direct) {
+        if (dtype == CIQ_F64)
+            e = launch_reduce_splits<double>(static_cast<const double*>(a.y), a.ysplit, pl.nsplit, s, p->n, s,
+                                             static_cast<double*>(y), ldy, stream);
+        else
+            e = launch_reduce_splits<float>(static_cast<const double*>(a.y), a.ysplit, pl.nsplit, s, p->n, s,
+                                            static_cast<float*>(y), ldy, stream);
+        if (e != hipSuccess) return CIQ_EHIP;
+    }
+    return CIQ_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1470,68 +1538,16 @@ int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double
 int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,
                    hipStream_t stream) {
     if (!valid_problem(p) || !valid_dtype(dtype) || !v || !y || s < 1 || ldv < s || ldy < s) return CIQ_EINVAL;
-    const int dp = pad_dims(p->d, dtype);
-    const size_t esz = (dtype == CIQ_F64) ? 8 : 4;
-    const int rpb = mvm_rows_per_block(dtype, s, 2);
-    const int nrb = (p->n + rpb - 1) / rpb;
-    const int nsplit = mvm_pick_nsplit(dtype, nrb, p->n, s);
-    // stream-ordered scratch: scaled points + FP64 split partials (the FP32
-    // product accumulates in FP64; the last step rounds to the caller's type)
-    const size_t xbytes = ((size_t)p->n * dp * sizeof(double) + 255) & ~size_t(255);
-    (void)esz;
-    const bool direct = (dtype == CIQ_F64 && nsplit == 1 && s <= 64);
-    const size_t ybytes = direct ? 0 : (size_t)nsplit * p->n * s * sizeof(double);
+    const KmvmPlan pl = kmvm_plan(p, dtype, s);
+    // stream-ordered scratch: scaled points + FP64 split partials
     void* buf = nullptr;
-    if (hipMallocAsync(&buf, xbytes + ybytes, stream) != hipSuccess) {
+    if (hipMallocAsync(&buf, pl.xbytes + pl.ybytes, stream) != hipSuccess) {
         (void)hipGetLastError();
         return CIQ_ENOMEM;
     }
-    double scale[CIQ_MAX_D];
-    point_scale(p, dtype, scale);
-    double ones[CIQ_MAX_D];
-    for (int k = 0; k < CIQ_MAX_D; ++k) ones[k] = 1.0;
-    hipError_t e;
-    if (dtype == CIQ_F64)
-        e = launch_prep<double>(static_cast<const double*>(p->x), p->n, p->d, dp, ones, static_cast<double*>(buf),
-                                stream);
-    else
-        e = launch_prep<float>(static_cast<const float*>(p->x), p->n, p->d, dp, ones, static_cast<double*>(buf),
-                               stream);
-    if (e != hipSuccess) return CIQ_EHIP;
-    MvmArgs a{};
-    a.xh = buf;
-    a.v = v;
-    a.y = direct ? y : static_cast<void*>(static_cast<char*>(buf) + xbytes);
-    a.ysplit = direct ? 0 : (long long)p->n * s;
-    a.ldv = ldv;
-    a.ldy = direct ? ldy : s;
-    a.s = s;
-    a.kernel = p->kernel;
-    a.dp = dp;
-    a.nsplit = nsplit;
-    a.rt = 2;
-    a.ard = 0;
-    for (int k = 0; k < CIQ_MAX_D; ++k) {
-        a.scale[k] = (k < p->d) ? scale[k] : 0.0;
-        if (k < p->d && scale[k] != scale[0]) a.ard = 1;
-    }
-    a.pscale = nullptr;
-    a.n = p->n;
-    a.o2 = p->outputscale;
-    a.s2 = p->noise;
-    a.nrb = nrb;
-    if (launch_mvm(dtype, a, stream) != hipSuccess) return CIQ_EHIP;
-    if (!direct) {
-        if (dtype == CIQ_F64)
-            e = launch_reduce_splits<double>(static_cast<const double*>(a.y), a.ysplit, nsplit, s, p->n, s,
-                                             static_cast<double*>(y), ldy, stream);
-        else
-            e = launch_reduce_splits<float>(static_cast<const double*>(a.y), a.ysplit, nsplit, s, p->n, s,
-                                            static_cast<float*>(y), ldy, stream);
-        if (e != hipSuccess) return CIQ_EHIP;
-    }
+    const int rc = kmvm_run(p, dtype, v, s, ldv, y, ldy, pl, buf, stream);
     if (hipFreeAsync(buf, stream) != hipSuccess) return CIQ_EHIP;
-    return CIQ_OK;
+    return rc;
 }
 
 int ciq_kernel_mvm_resident(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,

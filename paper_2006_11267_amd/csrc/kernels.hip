@@ -174,13 +174,24 @@ __host__ __device__ inline int col_tile(int s) {
 // everywhere (colsum_kernel, and the consumers when fuse_sums is set): lane r
 // of 16 sums blocks r, r + 16, ...; then the 16 lane sums are added in lane
 // order. Fused and separate column sums are therefore bitwise equal.
-// Lane sum r (of 16): partials of blocks r, r + 16, ...
+// Lane sum r (of 16): partials of blocks r, r + 16, ... added in that order
+// (eight loads issued before their adds).
 __device__ inline double colsum_lane(const Dev& d, int k, int g, int r) {
     const int p = g / d.s, c = g - p * d.s;
     const double* base = d.dots + ((long long)p * d.dots_blocks * d.s + c) * 2 + k;
     const long long stride = (long long)d.s * 2;
     double acc = 0.0;
-    for (int b = r; b < d.dots_blocks; b += 16) acc += base[(long long)b * stride];
+    for (int b0 = r; b0 < d.dots_blocks; b0 += 128) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + 16 * u;
+            v[u] = (b < d.dots_blocks) ? base[(long long)b * stride] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b0 + 16 * u < d.dots_blocks) acc += v[u];
+    }
     return acc;
 }
 
@@ -220,7 +231,7 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit
     const int c = blockIdx.y * TS + cl;
     double al = 0.0;
     if (q != nullptr && phase == 1) {
-        if (d.fuse_sums) {       // alpha_j of this block's columns from the phase-0 partials
+        if (d.fuse_sums & 2) {   // alpha_j of this block's columns from the phase-0 partials
             if (c < s)
                 for (int r = rl; r < 16; r += RL) lsum[r * TS + cl] = colsum_lane(d, 0, p * s + c, r);
             __syncthreads();
@@ -234,21 +245,40 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit
     if (c < s) {
         const int g = p * s + c;
         const double bj = (q != nullptr) ? d.beta_cur[g] : 0.0;
-        // rows i, i + G, i + 2G, ... (G = gridDim.x * RL) in that order; four
-        // rows' loads are issued before their arithmetic (memory-level
-        // parallelism with one block per CU), the summation order unchanged
-        constexpr int U = 4;
+        // rows i, i + G, i + 2G, ... (G = gridDim.x * RL) in that order; the
+        // split partials of two rows are all requested before they are added
+        // (in split order), so their loads are in flight together
+        constexpr int U = 2, MS = 16;
         const int G = gridDim.x * RL;
         for (int i0 = blockIdx.x * RL + rl; i0 < n; i0 += U * G) {
             double yv[U];
+            if (nsplit <= MS) {
+                double part[U][MS];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * G;
-                yv[u] = 0.0;
-                if (i < n) {
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * G;
                     const long long idx = (long long)(off + i) * s + c;
-                    yv[u] = (double)y[idx];
-                    for (int k = 1; k < nsplit; ++k) yv[u] += (double)y[k * ysplit + idx];
+#pragma unroll
+                    for (int k = 0; k < MS; ++k)
+                        part[u][k] = (i < n && k < nsplit) ? (double)y[k * ysplit + idx] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    yv[u] = part[u][0];
+#pragma unroll
+                    for (int k = 1; k < MS; ++k)
+                        if (k < nsplit) yv[u] += part[u][k];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * G;
+                    yv[u] = 0.0;
+                    if (i < n) {
+                        const long long idx = (long long)(off + i) * s + c;
+                        yv[u] = (double)y[idx];
+                        for (int k = 1; k < nsplit; ++k) yv[u] += (double)y[k * ysplit + idx];
+                    }
                 }
             }
 #pragma unroll
@@ -309,7 +339,9 @@ __global__ __launch_bounds__(1024) void colsum_kernel(Dev d, int k) {
 }
 
 hipError_t launch_colsum(const Dev& d, int k, hipStream_t st) {
-    if (d.fuse_sums) return hipSuccess;     // the consumers sum the partials themselves
+    // the consumers sum the partials themselves: alpha in phase 1 (bit 2),
+    // both sums in the scalar stage (bit 1)
+    if ((k == 0 && (d.fuse_sums & 2)) || (k == 1 && (d.fuse_sums & 1))) return hipSuccess;
     hipLaunchKernelGGL(colsum_kernel, dim3((d.ncol + 63) / 64), dim3(1024), 0, st, d, k);
     return hipGetLastError();
 }
@@ -330,7 +362,7 @@ template hipError_t launch_dots<double>(const Dev&, double*, long long, int, con
 __global__ __launch_bounds__(1024) void scalar_init_kernel(Dev d) {
     __shared__ int any;
     __shared__ double sh[1024];
-    if (d.fuse_sums) block_colsums(d, 1, threadIdx.x, blockDim.x, sh);
+    if (d.fuse_sums & 1) block_colsums(d, 1, threadIdx.x, blockDim.x, sh);
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
     const int ncol = d.ncol, Q = d.Q;
@@ -495,7 +527,7 @@ __global__ __launch_bounds__(1024) void scalar_kernel(Dev d) {
         if (threadIdx.x == 0) d.st->live = 0;
         return;
     }
-    if (d.fuse_sums) {      // column sums of both inner products' partials
+    if (d.fuse_sums & 1) {  // column sums of both inner products' partials
         block_colsums(d, 0, threadIdx.x, blockDim.x, sh);
         block_colsums(d, 1, threadIdx.x, blockDim.x, sh);
     }
