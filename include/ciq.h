@@ -87,6 +87,7 @@ extern "C" {
 #define CIQ_MAX_D   16   /* input dimensions                                        */
 #define CIQ_MAX_RANK 1024 /* preconditioner rank                                    */
 #define CIQ_MAX_OBS  4096 /* observations of ciq_posterior_mvm                       */
+#define CIQ_NOALLOC_SCRATCH_BYTES (64u << 20) /* static scratch of ciq_kernel_mvm_noalloc */
 
 /* One kernel matrix K = outputscale * k(X, X) + noise * I. */
 typedef struct ciq_problem {
@@ -208,6 +209,26 @@ int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double
  */
 int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ldv,
                    void* y, int ldy, hipStream_t stream);
+
+/*
+ * ciq_kernel_mvm without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and launch configuration, with the
+ * scaled points and the FP64 split partials in a static device array of
+ * CIQ_NOALLOC_SCRATCH_BYTES per GPU (reserved when the library is loaded,
+ * held until the process ends) instead of stream-ordered allocations.
+ * Results equal ciq_kernel_mvm's. Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (different streams or host threads
+ * without ordering) race and give wrong results; calls on one stream are
+ * ordered. The caller still supplies v and y.
+ * Asynchronous on `stream`. Errors: as for ciq_kernel_mvm, and CIQ_EINVAL when
+ * n * d_pad * 8 (rounded up to 256) + nsplit * n * s * 8 bytes exceed
+ * CIQ_NOALLOC_SCRATCH_BYTES (d_pad: d padded to 4/6/8/10/12/16; nsplit <= 8,
+ * the split of the column range the kernel uses; CIQ_F64 with one split and
+ * s <= 64 needs no partials); CIQ_EHIP if the array's address cannot be taken.
+ */
+int ciq_kernel_mvm_noalloc(const ciq_problem* p, int dtype, const void* v, int s, int ldv,
+                           void* y, int ldy, hipStream_t stream);
 
 /*
  * Y = K V by the resident-matrix product the solvers use when

@@ -12,6 +12,7 @@ from .ops import (  # noqa: F401
     ciq_invsqrt_mvm,
     ciq_invsqrt_mvm_batched,
     ciq_kernel_mvm,
+    ciq_kernel_mvm_noalloc,
     ciq_kernel_mvm_resident,
     ciq_pivoted_cholesky,
     ciq_posterior_mvm,

@@ -21,6 +21,7 @@ CIQ_MAX_Q = 64
 CIQ_MAX_D = 16
 CIQ_MAX_RANK = 1024
 CIQ_MAX_OBS = 4096
+CIQ_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 KERNELS = {"rbf": CIQ_KERNEL_RBF, "matern52": CIQ_KERNEL_MATERN52}
 DTYPES = {"f64": CIQ_F64, "f32": CIQ_F32, "bf16x3": CIQ_BF16X3, "f16x3": CIQ_F16X3}
@@ -118,6 +119,7 @@ PROTOTYPES = {
     "ciq_setup": (_I, [_D, _D, _I, _PD, _PD]),
     "ciq_kernel_mvm": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),
     "ciq_kernel_mvm_resident": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),
+    "ciq_kernel_mvm_noalloc": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),
     "ciq_eig_bounds": (_I, [ctypes.POINTER(ciq_problem), _I, _I, _VP, ctypes.c_uint64, _PD, _PD, _VP]),
     "ciq_invsqrt_mvm": (_I, [ctypes.POINTER(ciq_problem), ctypes.POINTER(ciq_opts), _VP, _I, _I, _VP, _I,
                              _VP, ctypes.POINTER(ciq_info), _VP]),

@@ -1508,6 +1508,29 @@ int kmvm_run(const ciq_problem* p, int dtype, const void* v, int s, int ldv, voi
     return CIQ_OK;
 }
 
+// Scratch of ciq_kernel_mvm_noalloc: a static device array (one copy per GPU,
+// held until the process ends). Host code never passes `scratch` itself (on
+// the host it names a stand-in, not device memory): its device address is
+// taken once per device with hipGetSymbolAddress, with that device current,
+// and only that address is used.
+static __device__ __align__(256) unsigned char scratch[CIQ_NOALLOC_SCRATCH_BYTES];
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(int dev, void** out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return CIQ_EHIP;
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return CIQ_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1548,6 +1571,18 @@ int ciq_kernel_mvm(const ciq_problem* p, int dtype, const void* v, int s, int ld
     const int rc = kmvm_run(p, dtype, v, s, ldv, y, ldy, pl, buf, stream);
     if (hipFreeAsync(buf, stream) != hipSuccess) return CIQ_EHIP;
     return rc;
+}
+
+int ciq_kernel_mvm_noalloc(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,
+                           hipStream_t stream) {
+    if (!valid_problem(p) || !valid_dtype(dtype) || !v || !y || s < 1 || ldv < s || ldy < s) return CIQ_EINVAL;
+    const KmvmPlan pl = kmvm_plan(p, dtype, s);
+    if (pl.xbytes + pl.ybytes > (size_t)CIQ_NOALLOC_SCRATCH_BYTES) return CIQ_EINVAL;
+    int dev;
+    STCHK(get_device(&dev));
+    void* buf = nullptr;
+    STCHK(noalloc_scratch(dev, &buf));
+    return kmvm_run(p, dtype, v, s, ldv, y, ldy, pl, buf, stream);
 }
 
 int ciq_kernel_mvm_resident(const ciq_problem* p, int dtype, const void* v, int s, int ldv, void* y, int ldy,

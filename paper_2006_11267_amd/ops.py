@@ -100,6 +100,24 @@ def ciq_kernel_mvm(problem: Problem, v: torch.Tensor, precision: Optional[str] =
     return y.reshape(v.shape)
 
 
+def ciq_kernel_mvm_noalloc(problem: Problem, v: torch.Tensor, y: torch.Tensor,
+                           precision: Optional[str] = None) -> torch.Tensor:
+    """Y = K V into the caller's y with no device allocation inside the call
+    (static scratch; on the current stream, asynchronous)."""
+    lib = L.load()
+    code = _dtype_code(problem.x, precision)
+    v2 = v if v.dim() == 2 else v.reshape(-1, 1)
+    y2 = y if y.dim() == 2 else y.reshape(-1, 1)
+    if y2.shape != v2.shape or y2.dtype != _elem_dtype(code) or not y2.is_cuda:
+        raise ValueError("y must be a device tensor of v's shape and the dtype's element type")
+    p, keep = problem.c_struct()
+    L.check(lib.ciq_kernel_mvm_noalloc(ctypes.byref(p), code, ctypes.c_void_p(v2.data_ptr()), v2.shape[1],
+                                       v2.stride(0), ctypes.c_void_p(y2.data_ptr()), y2.stride(0), _stream()),
+            "ciq_kernel_mvm_noalloc")
+    del keep
+    return y
+
+
 def ciq_kernel_mvm_resident(problem: Problem, v: torch.Tensor, precision: Optional[str] = None) -> torch.Tensor:
     """Y = K V through the solvers' resident-matrix product (K written once for
     the call, then streamed); synchronous."""
