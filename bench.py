@@ -10,8 +10,14 @@ in device memory before the timed region.
 Accuracy: the metric counts columns delivered at relative error <= 1e-4. At
 this conditioning (kappa ~ 2.5e6) a MINRES stopping tolerance of 1e-4 leaves
 up to ~8e-4 error in K^{1/2}B, so the default stopping tolerance is 5e-6, and
-after the timed steps the run checks the last output's first 16 columns
-against the FP64 path run to tol 1e-10 (untimed) and reports the error.
+after the timed steps the run compares the last output's first 8 columns with
+the CPU FP64 oracle's K^{1/2}B for them (msMINRES-CIQ to relative residual
+1e-10, stored in tests/golden by an oracle-only script) and reports the error.
+
+Precision form: after the FP32 line's steps the same workload runs with the
+split FP16 resident matrix (CIQ_F16X3), timed and checked the same way, and
+its columns/s, accuracy and HBM roofline are reported beside the FP32 line
+("precision_form").
 
 Default path: the kernel matrix is evaluated once per call in FP64, rounded
 to FP32 and kept resident in HBM (10 GB); every product streams it through
@@ -34,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}   # MI355X dense matrix peaks
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 # HBM bytes per launch of the streamed resident-K products at this workload
 # (N = 50,000, S = 64): FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
 # runs of `bench.py --counters [--precision f64]`, each scaled by the same
@@ -41,6 +48,7 @@ MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0
 # (profiles/mvm_kt*_kernel_matern52_n50000_s64_hbm_traffic.md).
 KT_TRAFFIC_BYTES = {"f64": 2.1359e10, "f32": 1.0659e10}
 METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
+HBM_PEAK_GBS = 8000.0
 
 
 def log(msg: str) -> None:
@@ -79,6 +87,56 @@ def cpu_baseline(p, iters: int, q: int, sample_rows: int = 12288) -> dict:
                    f"msMINRES vector steps ({2 * t_vec:.1f}s), extrapolated to {iters} iterations + 1 product "
                    f"(est. {t_solve:.0f}s per solve of {s} columns)"),
     }
+
+
+def roofline(precision: str, cached: bool, n: int, s: int, avg_ms: float, launches: int) -> dict:
+    """Roofline of the kernel product from its live HIP-event timing. The FP32
+    and FP64 products are MFMA-bound: 2 N^2 S flops per launch against the
+    dense MFMA peak of their precision. The resident split FP16 product is
+    HBM-bound: its algorithmic bytes per launch are the matrix (4 bytes per
+    entry, N^2 entries), the split operand (4 N S) and the FP64 result (8 N S),
+    against 8 TB/s."""
+    if precision == "f16x3" and cached:
+        bytes_ = 4.0 * n * n + 12.0 * n * s
+        achieved = bytes_ / (avg_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": KT_TRAFFIC_BYTES.get("f16x3") if (n, s) == (50000, 64) else None,
+                "kernel": "mvm_kt16_kernel", "avg_ms": avg_ms, "launches": launches,
+                "algorithmic_bytes": bytes_,
+                "mfma_tflops": 3 * 2.0 * n * n * s / (avg_ms * 1e-3) / 1e12}
+    flops = 2.0 * n * n * s * (3 if precision in ("bf16x3", "f16x3") else 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision]
+    kernel = ({"f64": "mvm_kt_kernel", "f32": "mvm_kt32_kernel"}[precision] if cached else
+              {"f64": "mvm_f64mfma_kernel", "f32": "mvm_f32_kernel"}.get(precision, "mvm_x3_kernel"))
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": KT_TRAFFIC_BYTES.get(precision) if cached and (n, s) == (50000, 64) else None,
+            "kernel": kernel, "avg_ms": avg_ms, "launches": launches}
+
+
+def oracle_reference(n: int, s: int, mode: str = "sqrt"):
+    """The CPU oracle's K^{1/2}B (or K^{-1/2}B) for the first columns of the
+    large Matern workload, if the stored reference matches (n, s); else None."""
+    meta_path = os.path.join(GOLDEN, "matern52_n50000_s8_reference.json")
+    if n != 50000 or not os.path.exists(meta_path):
+        return None, None
+    meta = json.load(open(meta_path))
+    ref = np.load(os.path.join(GOLDEN, f"matern52_n50000_s8_{mode}.npy"), allow_pickle=False)
+    k = min(ref.shape[1], s)
+    return ref[:, :k], meta
+
+
+def accuracy_vs_oracle(out, n, s):
+    ref, meta = oracle_reference(n, s)
+    if ref is None:
+        return None
+    k = ref.shape[1]
+    o = out[:, :k].double().cpu().numpy()
+    rel = np.linalg.norm(o - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    return {"max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)), "columns": k,
+            "reference": (f"CPU FP64 oracle msMINRES-CIQ, Q = {meta['q']}, relative residual {meta['tol']:g} "
+                          f"({meta['iters']} iterations), tests/golden")}
 
 
 def _rel(out, ref):
@@ -265,6 +323,33 @@ def other_workload(args, torch, ciq, workloads) -> int:
     return 0
 
 
+def precision_form(args, ciq, torch, p, x, b, q, tol, n, s) -> dict:
+    """The same workload with the split FP16 resident matrix (CIQ_F16X3): one
+    warm-up call, then args.form_steps timed calls, checked against the oracle."""
+    kw = dict(q=q, max_iter=args.max_iter, tol=tol, seed=4001, kernel_cache=args.kernel_cache, precision="f16x3")
+    out, info, _ = ciq.ciq_sqrt_mvm(p, b, **kw)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    infos = []
+    start.record()
+    for _ in range(args.form_steps):
+        out, info, _ = ciq.ciq_sqrt_mvm(p, b, profile=True, **kw)
+        infos.append(info)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(stop) / args.form_steps
+    avg_ms = sum(i["mvm_ms"] for i in infos) / max(sum(i["mvm_timed"] for i in infos), 1)
+    acc = accuracy_vs_oracle(out, n, s) if args.check_cols > 0 else None
+    log(f"precision form f16x3: {ms_step:.1f} ms/step, iters={info['iters']}, product {avg_ms:.3f} ms"
+        + (f", max rel err {acc['max_rel_err']:.2e}" if acc else ""))
+    return {"precision": "f16x3", "value": s / (ms_step * 1e-3), "unit": "columns/s", "steps": args.form_steps,
+            "ms_per_step": ms_step, "iters": info["iters"], "converged": info["converged"],
+            "kernel_cached": info["kernel_cached"], "accuracy": acc,
+            "roofline": roofline("f16x3", info["kernel_cached"], n, s, avg_ms,
+                                 sum(i["mvm_timed"] for i in infos))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +363,8 @@ def main() -> int:
                     help="keep K resident in HBM for the call (auto: when it fits)")
     ap.add_argument("--n", type=int, default=None, help="shrink N (testing only)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--form-steps", type=int, default=2,
+                    help="timed calls of the split FP16 precision form reported beside the FP32 line (0: skip)")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter profiles: a plain device copy of known size, then one "
                          "solve of the bench problem cut to 4 msMINRES iterations (same launch configuration)")
@@ -356,8 +443,10 @@ def main() -> int:
     log(f"timed: {ms_step:.1f} ms/step, iters={info['iters']}, converged={info['converged']}, "
         f"max_rel_residual={info['max_rel_residual']:.2e}")
 
-    accuracy = None
-    if args.check_cols > 0:
+    accuracy = accuracy_vs_oracle(out, n, s) if args.check_cols > 0 and args.precond_rank == 0 else None
+    if accuracy is not None:
+        log(f"accuracy vs oracle on {accuracy['columns']} columns: max {accuracy['max_rel_err']:.2e}")
+    elif args.check_cols > 0:
         # reference: the FP64 path on the same (rounded) inputs, same bounds,
         # tol 1e-10 (preconditioned: the same rank, hence the same factor of
         # the same FP64 points, so the same rotation)
@@ -379,11 +468,10 @@ def main() -> int:
     mvm_ms = sum(i["mvm_ms"] for i in infos)
     mvm_n = sum(i["mvm_timed"] for i in infos)
     avg_ms = mvm_ms / max(mvm_n, 1)
-    # algorithmic tile x V contraction per launch; the split forms run it as
-    # three half-precision MFMA products
-    flops = 2.0 * n * n * s * (3 if args.precision in ("bf16x3", "f16x3") else 1)
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    peak = MFMA_PEAK_TFLOPS[args.precision]
+
+    form = None
+    if args.precision == "f32" and args.precond_rank == 0 and args.form_steps > 0:
+        form = precision_form(args, ciq, torch, prob, x, b, q, tol, n, s)
 
     res = {
         "metric": METRIC,
@@ -408,17 +496,10 @@ def main() -> int:
             **({"precond_pivots": info["precond_rank"], "precond_trace": info["precond_trace"],
                 "output": "R B with R R^T = K (K^{1/2} B up to a rotation)"} if args.precond_rank else {}),
         },
-        "roofline": {
-            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": (KT_TRAFFIC_BYTES.get(args.precision) if info["kernel_cached"] and (n, s) == (50000, 64)
-                        else None),
-            "kernel": ({"f64": "mvm_kt_kernel", "f32": "mvm_kt32_kernel", "f16x3": "mvm_kt16_kernel"}[args.precision]
-                       if info["kernel_cached"] else
-                       {"f64": "mvm_f64mfma_kernel", "f32": "mvm_f32_kernel"}.get(args.precision, "mvm_x3_kernel")),
-            "avg_ms": avg_ms, "launches": mvm_n,
-        },
+        "roofline": roofline(args.precision, info["kernel_cached"], n, s, avg_ms, mvm_n),
     }
+    if form is not None:
+        res["precision_form"] = form
     if not args.no_cpu:
         log("cpu baseline (oracle sample) ...")
         res["cpu_baseline"] = cpu_baseline(p, info["iters"], q)

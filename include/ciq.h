@@ -72,7 +72,7 @@ extern "C" {
                            ~1e-6 per product on the fly; with a resident K
                            (ciq_opts.kernel_cache) the FP64 entries are stored
                            split once, hi + 2^-11 lo (4 bytes per entry), and
-                           all four part products run on FP16 MFMA (~1e-7 per
+                           three part products run on FP16 MFMA (~1e-7 per
                            product, FP32-class); ciq_backward and the batched
                            call return CIQ_ENOTSUP for both split forms        */
 
@@ -239,7 +239,7 @@ int ciq_kernel_mvm_noalloc(const ciq_problem* p, int dtype, const void* v, int s
  * MFMA), CIQ_F32 (FP64 entries rounded once to FP32, FP32 MFMA, FP64 sums
  * across 64-column chunks), CIQ_F16X3 (FP64 entries split into FP16
  * hi + 2^-11 lo, V split likewise after a per-column power-of-two scale,
- * four part products on FP16 MFMA); CIQ_BF16X3 is CIQ_ENOTSUP.
+ * three part products on FP16 MFMA); CIQ_BF16X3 is CIQ_ENOTSUP.
  *   v, s, ldv, y, ldy: as for ciq_kernel_mvm.
  * Synchronous. Errors: as for ciq_kernel_mvm; CIQ_ENOMEM if the matrix does not
  * fit; CIQ_ENOTSUP for CIQ_BF16X3.

@@ -35,11 +35,13 @@
 // Unit-scale entries lie in [0, 1]: hi + 2^-11 lo carries 22 significant
 // bits (absolute error <= 2^-22 |k| for normal hi, ~1e-11 below FP16's
 // normal range). The product multiplies the split operand vh + 2^-11 vl
-// (op16_index layout) by all four part pairs,
-//     K V ~ Kh Vh + 2^-11 (Kh Vl + Kl Vh) + 2^-22 Kl Vl,
+// (op16_index layout) by three part pairs,
+//     K V ~ Kh Vh + 2^-11 (Kh Vl + Kl Vh),
 // on v_mfma_f32_16x16x32_f16 with FP32 accumulators (the hi x hi sum flushed
-// into FP64 after every 64-column chunk). Its bytes per entry equal the FP32
-// form's while its MFMA work is a fifth, so it streams K at HBM speed.
+// into FP64 after every 64-column chunk); the dropped 2^-22 Kl Vl term is
+// ~2^-24 relative, below the 22-bit representation error. Its bytes per entry
+// equal the FP32 form's while its MFMA work is a seventh, so it streams K at
+// close to HBM speed.
 #include "mvm_mfma.h"
 
 namespace ciq {
@@ -458,8 +460,10 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
 // 64-column chunk the block stages the chunk's split V operands (NSB column
 // blocks x 2 k-steps x hi/lo, already in B-operand order) in LDS with 16-byte
 // copies, and each wave contracts its RT tiles' split K operands (four
-// 16-byte loads per lane and tile, the next chunk's in flight) with all four
-// part pairs.
+// 16-byte loads per lane and tile, the next chunk's in flight) with three
+// part pairs. For 128-row blocks the wide launches use eight waves of one
+// tile each rather than four of two: the V staging is shared by twice the
+// rows at 128 VGPRs (four waves per SIMD) instead of 256 (one).
 template <int NSB, int RT, int WAVES, int KD>
 __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
     constexpr int NT = 64 * WAVES;
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
     const int c0 = (int)(((long long)split * nchunk) / nsplit);
     const int c1 = (int)(((long long)(split + 1) * nchunk) / nsplit);
 
-    floatx4 ah[RT][NSB], ax[RT][NSB], al[RT][NSB];
+    floatx4 ah[RT][NSB], ax[RT][NSB];
     double accd[RT][NSB][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -497,7 +501,6 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
         for (int sb = 0; sb < NSB; ++sb) {
             ah[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
             ax[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            al[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
         }
@@ -542,12 +545,11 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
                     ah[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk], bh, ah[rt][sb], 0, 0, 0);
                     ax[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk], bl, ax[rt][sb], 0, 0, 0);
                     ax[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk + 1], bh, ax[rt][sb], 0, 0, 0);
-                    al[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk + 1], bl, al[rt][sb], 0, 0, 0);
                 }
             }
         }
-        // the hi x hi sum leaves FP32 after every chunk; the cross sums are
-        // 2^-11 and 2^-22 smaller and stay in FP32 for the whole range
+        // the hi x hi sum leaves FP32 after every chunk; the cross sum is
+        // 2^-11 smaller and stays in FP32 for the whole range
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
             if (c + q < c1) chunk(c + q, kq[q], kq[(q + KD - 1) % KD]);
     }
 
-    constexpr double k11 = 1.0 / 2048.0, k22 = 1.0 / 4194304.0;
+    constexpr double k11 = 1.0 / 2048.0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
                 const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;   // 16x16 accumulator layout
                 if (i < n && cc < s) {
                     const double vi = a.vcol_inv ? a.vcol_inv[cc] : a.vinv;
-                    const double kv = accd[rt][sb][r] + ((double)ax[rt][sb][r] * k11 + (double)al[rt][sb][r] * k22);
+                    const double kv = accd[rt][sb][r] + (double)ax[rt][sb][r] * k11;
                     double val = o2 * kv * vi;
                     if (split == 0) val = fma(s2, v[(long long)i * ldv + cc], val);
                     y[(long long)i * ldy + cc] = val;
@@ -642,21 +644,25 @@ hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
 }
 
 template <typename K>
-static int occupancy_of(K kernel) {
+static int occupancy_of(K kernel, int threads = 256) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     return nb;
 }
 
+// rt = 1: 64-row blocks of four one-tile waves; rt = 2: 128-row blocks, as
+// eight one-tile waves (one column block: four two-tile waves)
 template <int NSB>
 hipError_t launch_kt16_nsb(const MvmArgs& a, int grid, hipStream_t st) {
     if (a.rt == 1 || NSB > 4)
         hipLaunchKernelGGL((mvm_kt16_kernel<NSB, 1, 4, 2>), dim3(grid), dim3(256), 0, st, a);
+    else if (NSB == 1)
+        hipLaunchKernelGGL((mvm_kt16_kernel<1, 2, 4, 2>), dim3(grid), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((mvm_kt16_kernel<NSB, (NSB > 4 ? 1 : 2), 4, 2>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((mvm_kt16_kernel<(NSB < 2 ? 2 : NSB), 1, 8, 2>), dim3(grid), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 
@@ -668,7 +674,8 @@ int kt_blocks_per_cu(int dtype, int nsb, int rt) {
             return k == 1 ? occupancy_of(mvm_kt16_kernel<1, 1, 4, 2>)
                           : (k == 2 ? occupancy_of(mvm_kt16_kernel<2, 1, 4, 2>) : occupancy_of(mvm_kt16_kernel<4, 1, 4, 2>));
         return k == 1 ? occupancy_of(mvm_kt16_kernel<1, 2, 4, 2>)
-                      : (k == 2 ? occupancy_of(mvm_kt16_kernel<2, 2, 4, 2>) : occupancy_of(mvm_kt16_kernel<4, 2, 4, 2>));
+                      : (k == 2 ? occupancy_of(mvm_kt16_kernel<2, 1, 8, 2>, 512)
+                                : occupancy_of(mvm_kt16_kernel<4, 1, 8, 2>, 512));
     }
     const bool f32 = (dtype == CIQ_F32);
     if (f32) {

@@ -232,7 +232,7 @@ def test_split_forms_against_exact(prec, cache, bar):
     """The split-operand BF16 / FP16 products inside a full CIQ solve: the
     error against the exact K^{-1/2}B and K^{1/2}B (eigendecomposition) is
     stated per form, bounded loosely here (kappa ~ 2e4). With the resident
-    split FP16 matrix (22-bit entries, four part products) the bar is the
+    split FP16 matrix (22-bit entries, three part products) the bar is the
     FP32 path's."""
     torch = torch_cuda()
     ciq = ciq_module()

@@ -85,7 +85,7 @@ def test_mvm_full_size_sampled_rows(kind, n, d, s, prec):
 # Resident-matrix products (the solvers' streamed K, ciq_kernel_mvm_resident):
 # FP64 entries; FP32: entries rounded once to FP32, FP32 MFMA with FP64 sums
 # across 64-column chunks; split FP16: entries and V each kept to ~22 bits
-# (hi + 2^-11 lo, V after a per-column power-of-two scale), all four part
+# (hi + 2^-11 lo, V after a per-column power-of-two scale), three part
 # products, so the bar is a few units of 2^-22 ~ 2.4e-7.
 RESIDENT_TOL = {"f64": 1e-12, "f32": 1e-6, "f16x3": 2e-6}
 
