@@ -373,6 +373,29 @@ int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* 
                      ciq_info* info_solve, hipStream_t stream);
 
 /*
+ * One natural-gradient step of the whitened SVGP in natural parameters
+ * (App. E, the O(M^2) update): with a_b = Kzz^{-1/2} k_Zx_b and mean_b for a
+ * minibatch of nb points (the a_out and mean of ciq_svgp_predict) and the
+ * likelihood's constants c_mean_b = d ELL_b / d mean_b, c_var_b = d ELL_b / d var_b
+ * (Gaussian likelihood: (y_b - mean_b) / noise and -1 / (2 noise)), the
+ * ELBO gradient in the expectation parameters is
+ *   d ELBO / d eta = scale sum_b (c_mean_b - 2 c_var_b mean_b) a_b - theta,
+ *   d ELBO / d H   = scale sum_b c_var_b a_b a_b^T - I/2 - Theta
+ * (scale = N / nb for a minibatch of N data; the KL derivatives are theta and
+ * I/2 + Theta), and the step ascends the ELBO:
+ *   theta += step * d ELBO / d eta,   Theta += step * d ELBO / d H.
+ * The rank-nb update of Theta runs on FP64 MFMA (2 M^2 nb flops).
+ *   a: device M x nb doubles (row-major); mean, c_mean, c_var: device nb doubles;
+ *   theta: device M doubles, Theta: device M x M doubles (row-major), both
+ *   updated in place.
+ * Synchronous. Errors: CIQ_EINVAL (M < 1, nb < 1, null pointers, non-finite
+ * scale or step), CIQ_ENOMEM, CIQ_EHIP.
+ */
+int ciq_svgp_ngd_step(int M, int nb, const double* a, const double* mean, const double* c_mean,
+                      const double* c_var, double scale, double step, double* theta, double* Theta,
+                      hipStream_t stream);
+
+/*
  * Posterior covariance root for Thompson sampling (Sec. 5.2): with candidates
  * X* (cand->x, T = cand->n points) and observations X (x_obs, n_obs points)
  * under the same kernel,

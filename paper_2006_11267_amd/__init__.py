@@ -18,6 +18,7 @@ from .ops import (  # noqa: F401
     ciq_posterior_mvm,
     ciq_setup,
     ciq_sqrt_mvm,
+    ciq_svgp_ngd_step,
     ciq_svgp_predict,
     ciq_version,
     ciq_backward,

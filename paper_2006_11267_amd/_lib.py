@@ -136,6 +136,7 @@ PROTOTYPES = {
                          ctypes.POINTER(ciq_info), _VP]),
     "ciq_svgp_predict": (_I, [ctypes.POINTER(ciq_problem), _VP, _I, _VP, _VP, ctypes.POINTER(ciq_opts), _I, _D, _VP,
                               _VP, _VP, ctypes.POINTER(ciq_info), ctypes.POINTER(ciq_info), _VP]),
+    "ciq_svgp_ngd_step": (_I, [_I, _I, _VP, _VP, _VP, _VP, _D, _D, _VP, _VP, _VP]),
     "ciq_posterior_mvm": (_I, [ctypes.POINTER(ciq_problem), _VP, _I, _D, _I, ctypes.POINTER(ciq_opts), _VP, _I, _I,
                                _VP, _I, ctypes.POINTER(ciq_info), _VP]),
 }

@@ -307,6 +307,12 @@ hipError_t launch_scale(const double* x, double alpha, double* y, long long n, h
 // mean[b] = theta . c_b, var[b] = kxx - a_b . a_b + a_b . c_b.
 hipError_t launch_svgp_stats(const double* a, const double* c, const double* theta, int M, int nb, double kxx,
                              double* mean, double* var, hipStream_t st);
+// Natural-gradient step operands: T (nb x M) = diag(step scale c_var) a^T,
+// u (nb) = step scale (c_mean - 2 c_var mean); a is M x nb row-major.
+hipError_t launch_ngd_prep(const double* a, const double* mean, const double* c_mean, const double* c_var, int M,
+                           int nb, double scale, double step, double* T, double* u, hipStream_t st);
+// A[i][i] += v for the M x M row-major A.
+hipError_t launch_diag_add(double* A, int M, double v, hipStream_t st);
 // Dense symmetric operator of a single-shift solve (SVGP: -2 Theta).
 struct DenseOp {
     const double* A;         // n x n, row-major

@@ -1886,6 +1886,30 @@ int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* 
     return CIQ_OK;
 }
 
+int ciq_svgp_ngd_step(int M, int nb, const double* a, const double* mean, const double* c_mean, const double* c_var,
+                      double scale, double step, double* theta, double* Theta, hipStream_t stream) {
+    if (M < 1 || nb < 1 || !a || !mean || !c_mean || !c_var || !theta || !Theta) return CIQ_EINVAL;
+    if (!std::isfinite(scale) || !std::isfinite(step)) return CIQ_EINVAL;
+    int dev;
+    STCHK(get_device(&dev));
+    ScratchLock lock(dev);
+    Sizer sz;
+    sz.take<double>((size_t)M * nb);
+    sz.take<double>(nb);
+    void* base = nullptr;
+    STCHK(scratch_reserve(dev, sz.off + 4096, &base));
+    Carver c(base);
+    double* T = c.take<double>((size_t)M * nb);
+    double* u = c.take<double>(nb);
+    HIPCHK(launch_ngd_prep(a, mean, c_mean, c_var, M, nb, scale, step, T, u, stream));
+    // Theta <- (1 - step) Theta + a T - (step / 2) I;  theta <- (1 - step) theta + a u
+    HIPCHK(launch_lr_apply(1.0 - step, Theta, M, a, nb, T, M, M, nb, M, Theta, M, nullptr, nullptr, nullptr, stream));
+    HIPCHK(launch_diag_add(Theta, M, -0.5 * step, stream));
+    HIPCHK(launch_lr_apply(1.0 - step, theta, 1, a, nb, u, 1, M, nb, 1, theta, 1, nullptr, nullptr, nullptr, stream));
+    HIPCHK(hipStreamSynchronize(stream));   // the scratch is reused by the next call
+    return CIQ_OK;
+}
+
 int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_out, int* piv_out,
                          double* trace_out, hipStream_t stream) {
     if (!valid_problem(p) || !valid_dtype(dtype) || !l_out || !piv_out) return CIQ_EINVAL;

@@ -601,6 +601,38 @@ hipError_t launch_svgp_stats(const double* a, const double* c, const double* the
     return hipGetLastError();
 }
 
+// Natural-gradient step operands (App. E): T[b][j] = w_b a[j][b] with
+// w_b = step scale c_var[b] (the rank-nb update of Theta), and
+// u[b] = step scale (c_mean[b] - 2 c_var[b] mean[b]) (the update of theta).
+__global__ void ngd_prep_kernel(const double* __restrict__ a, const double* __restrict__ mean,
+                                const double* __restrict__ c_mean, const double* __restrict__ c_var, int M, int nb,
+                                double scale, double step, double* __restrict__ T, double* __restrict__ u) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (long long)M * nb) {
+        const int b = (int)(e / M), j = (int)(e - (long long)b * M);
+        T[e] = step * scale * c_var[b] * a[(long long)j * nb + b];
+    }
+    if (e < nb) u[e] = step * scale * (c_mean[e] - 2.0 * c_var[e] * mean[e]);
+}
+
+__global__ void diag_add_kernel(double* __restrict__ A, int M, double v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) A[(long long)i * M + i] += v;
+}
+
+hipError_t launch_ngd_prep(const double* a, const double* mean, const double* c_mean, const double* c_var, int M,
+                           int nb, double scale, double step, double* T, double* u, hipStream_t st) {
+    const long long total = std::max((long long)M * nb, (long long)nb);
+    hipLaunchKernelGGL(ngd_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, mean, c_mean,
+                       c_var, M, nb, scale, step, T, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_add(double* A, int M, double v, hipStream_t st) {
+    hipLaunchKernelGGL(diag_add_kernel, dim3((M + 255) / 256), dim3(256), 0, st, A, M, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_pc_w(const Dev& d, double* y, const double* zc, const double* zp, hipStream_t st) {
     const long long total = (long long)d.rows_total * d.s;
     hipLaunchKernelGGL(pc_w_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, d, y, zc, zp);

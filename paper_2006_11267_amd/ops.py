@@ -277,6 +277,23 @@ def ciq_svgp_predict(inducing: Problem, x: torch.Tensor, theta: torch.Tensor, Th
     return mean, var, a, info.as_dict(), info_s.as_dict()
 
 
+def ciq_svgp_ngd_step(a: torch.Tensor, mean: torch.Tensor, c_mean: torch.Tensor, c_var: torch.Tensor,
+                      theta: torch.Tensor, Theta: torch.Tensor, scale: float, step: float):
+    """One App. E natural-gradient step, updating theta (M) and Theta (M x M)
+    in place from a (M x nb), mean, c_mean, c_var (nb); all float64 device
+    tensors. Returns (theta, Theta)."""
+    lib = L.load()
+    M, nb = a.shape
+    for t, shape in ((a, (M, nb)), (mean, (nb,)), (c_mean, (nb,)), (c_var, (nb,)), (theta, (M,)), (Theta, (M, M))):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError("float64 contiguous device tensors of the documented shapes are required")
+    L.check(lib.ciq_svgp_ngd_step(M, nb, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(mean.data_ptr()),
+                                  ctypes.c_void_p(c_mean.data_ptr()), ctypes.c_void_p(c_var.data_ptr()),
+                                  float(scale), float(step), ctypes.c_void_p(theta.data_ptr()),
+                                  ctypes.c_void_p(Theta.data_ptr()), _stream()), "ciq_svgp_ngd_step")
+    return theta, Theta
+
+
 def ciq_pivoted_cholesky(problem: Problem, rank: int):
     """Rank-`rank` partial pivoted Cholesky factor of outputscale * k(X, X):
     (Lbar as an n x rank float64 device tensor, pivots (numpy, -1 after a
