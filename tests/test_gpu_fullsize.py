@@ -161,7 +161,8 @@ def test_fp64_path_against_oracle(mode):
     meta, ref = _oracle_reference()
     torch = torch_cuda()
     ciq = ciq_module()
-    wl, prob, b = _problem(ciq, torch, np.float64, 8)
+    wl, prob, b = _problem(ciq, torch, np.float64, 64)
+    b = b[:, :ref[mode].shape[1]].contiguous()      # the reference's right-hand sides: B's first columns
     announce(f"fp64 path {mode} vs oracle reference n=50000 s=8 tol 1e-10")
     fn = ciq.ciq_sqrt_mvm if mode == "sqrt" else ciq.ciq_invsqrt_mvm
     out, info, _ = fn(prob, b, q=meta["q"], max_iter=20000, tol=meta["tol"],
