@@ -1,6 +1,9 @@
 // Host FP64 quadrature for K^{-1/2} (Appendix B; Alg. S2) and the small
 // symmetric eigensolver used by the extreme-eigenvalue estimate.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "ciq.h"
@@ -128,65 +131,117 @@ void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& evals, s
         for (int k = 0; k < n; ++k) v[(size_t)k * n + j] = vt[(size_t)j * n + k];
 }
 
+// Fork-join helpers of the eigensolver below: a team of host threads (the
+// caller is member 0) that meets at a sense-reversing spin barrier.
+namespace {
+class SpinBarrier {
+  public:
+    explicit SpinBarrier(int n) : n_(n) {}
+    void wait() {
+        const int gen = gen_.load(std::memory_order_acquire);
+        if (count_.fetch_add(1, std::memory_order_acq_rel) + 1 == n_) {
+            count_.store(0, std::memory_order_relaxed);
+            gen_.store(gen + 1, std::memory_order_release);
+        } else {
+            while (gen_.load(std::memory_order_acquire) == gen) std::this_thread::yield();
+        }
+    }
+
+  private:
+    const int n_;
+    std::atomic<int> count_{0};
+    std::atomic<int> gen_{0};
+};
+
+// Threads for an n x n problem: at most 16 (and the machine's count), one
+// per 48 rows, one below n = 128.
+int team_size(int n) {
+    if (n < 128) return 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int cap = (int)std::min(hw == 0 ? 1u : hw, 16u);
+    return std::max(1, std::min(cap, n / 48));
+}
+
+template <typename F>
+void run_team(int T, F&& f) {
+    std::vector<std::thread> th;
+    th.reserve(T > 1 ? T - 1 : 0);
+    for (int t = 1; t < T; ++t) th.emplace_back([&f, t] { f(t); });
+    f(0);
+    for (auto& x : th) x.join();
+}
+
+struct Givens {
+    int k;
+    double c, s;
+};
+}  // namespace
+
 // Eigenvalues/vectors of a symmetric matrix (row-major n x n, overwritten) for
 // the larger matrices of the preconditioner: Householder reduction to
 // tridiagonal form, then implicit symmetric QR steps with the Wilkinson shift
 // and deflation (Golub & Van Loan 8.3.1, 8.3.3), ~9 n^3 flops against the
-// ~30 n^3 of cyclic Jacobi. The orthogonal factors are accumulated as rows of
-// V^T, so every update runs over contiguous memory. Eigenvector j is column j
-// of v.
+// ~30 n^3 of cyclic Jacobi. The orthogonal factor V^T = G_last ... G_1
+// H_{n-3} ... H_0 is formed after both phases from the stored reflectors and
+// the recorded rotations: every factor acts on the columns of V^T one by one,
+// so a team of threads takes one slice of columns each. The reduction itself
+// splits its matrix-vector product and rank-2 update by rows. Each element
+// sees the same operations in the same order for any team size, so the
+// result does not depend on the thread count. Eigenvector j is column j of v.
 void sym_eig_tridiag(int n, std::vector<double>& a, std::vector<double>& evals, std::vector<double>& v) {
-    std::vector<double> vt((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) vt[(size_t)i * n + i] = 1.0;
-    std::vector<double> hv(n), p(n), w(n), u(n);
-    // ---- Householder reduction: A <- H_k A H_k on the trailing block, V^T <- H_k V^T
-    for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;
-        const double* x = &a[(size_t)k * n + k + 1];
-        double sig = 0.0;
-        for (int i = 0; i < m; ++i) sig += x[i] * x[i];
-        sig = std::sqrt(sig);
-        if (sig == 0.0) continue;
-        const double alpha = (x[0] >= 0.0) ? -sig : sig;
-        for (int i = 0; i < m; ++i) hv[i] = x[i];
-        hv[0] -= alpha;
-        double vv = 0.0;
-        for (int i = 0; i < m; ++i) vv += hv[i] * hv[i];
-        const double beta = 2.0 / vv;
-        double vp = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double* ai = &a[(size_t)(k + 1 + i) * n + k + 1];
-            double t = 0.0;
-            for (int j = 0; j < m; ++j) t += ai[j] * hv[j];
-            p[i] = beta * t;
-            vp += hv[i] * p[i];
+    const int T = team_size(n);
+    std::vector<double> hvs((size_t)n * n, 0.0);   // reflector k in row k, entries k+1..n-1
+    std::vector<double> betas(n, 0.0);             // 0: no reflector at step k
+    std::vector<double> p(n);
+    SpinBarrier bar(T);
+    // ---- Householder reduction: A <- H_k A H_k on the trailing block
+    run_team(T, [&](int t) {
+        std::vector<double> hv(n), w(n);
+        for (int k = 0; k + 2 < n; ++k) {
+            const int m = n - k - 1;
+            const double* x = &a[(size_t)k * n + k + 1];
+            double sig = 0.0;
+            for (int i = 0; i < m; ++i) sig += x[i] * x[i];
+            sig = std::sqrt(sig);
+            if (sig == 0.0) continue;                    // the same on every member
+            const double alpha = (x[0] >= 0.0) ? -sig : sig;
+            for (int i = 0; i < m; ++i) hv[i] = x[i];
+            hv[0] -= alpha;
+            double vv = 0.0;
+            for (int i = 0; i < m; ++i) vv += hv[i] * hv[i];
+            const double beta = 2.0 / vv;
+            const int i0 = (int)((long long)m * t / T), i1 = (int)((long long)m * (t + 1) / T);
+            for (int i = i0; i < i1; ++i) {
+                const double* ai = &a[(size_t)(k + 1 + i) * n + k + 1];
+                double s = 0.0;
+                for (int j = 0; j < m; ++j) s += ai[j] * hv[j];
+                p[i] = beta * s;
+            }
+            bar.wait();                                  // p complete
+            double vp = 0.0;
+            for (int i = 0; i < m; ++i) vp += hv[i] * p[i];
+            const double kc = 0.5 * beta * vp;
+            for (int i = 0; i < m; ++i) w[i] = p[i] - kc * hv[i];
+            bar.wait();                                  // p read by all before rows change
+            for (int i = i0; i < i1; ++i) {
+                double* ai = &a[(size_t)(k + 1 + i) * n + k + 1];
+                const double vi = hv[i], wi = w[i];
+                for (int j = 0; j < m; ++j) ai[j] -= vi * w[j] + wi * hv[j];
+            }
+            if (t == 0) {
+                betas[k] = beta;
+                for (int i = 0; i < m; ++i) hvs[(size_t)k * n + k + 1 + i] = hv[i];
+                a[(size_t)k * n + k + 1] = alpha;
+                for (int j = k + 2; j < n; ++j) a[(size_t)k * n + j] = 0.0;
+            }
+            bar.wait();                                  // rows updated before the next reflector
         }
-        const double kc = 0.5 * beta * vp;
-        for (int i = 0; i < m; ++i) w[i] = p[i] - kc * hv[i];
-        for (int i = 0; i < m; ++i) {
-            double* ai = &a[(size_t)(k + 1 + i) * n + k + 1];
-            const double vi = hv[i], wi = w[i];
-            for (int j = 0; j < m; ++j) ai[j] -= vi * w[j] + wi * hv[j];
-        }
-        a[(size_t)k * n + k + 1] = a[(size_t)(k + 1) * n + k] = alpha;
-        for (int j = k + 2; j < n; ++j) a[(size_t)k * n + j] = a[(size_t)j * n + k] = 0.0;
-        // V^T rows k+1.. <- H_k applied from the left
-        for (int j = 0; j < n; ++j) u[j] = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double* ri = &vt[(size_t)(k + 1 + i) * n];
-            const double vi = hv[i];
-            for (int j = 0; j < n; ++j) u[j] += vi * ri[j];
-        }
-        for (int i = 0; i < m; ++i) {
-            double* ri = &vt[(size_t)(k + 1 + i) * n];
-            const double f = beta * hv[i];
-            for (int j = 0; j < n; ++j) ri[j] -= f * u[j];
-        }
-    }
+    });
     std::vector<double> d(n), e(n > 1 ? n - 1 : 1, 0.0);
     for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
     for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)i * n + i + 1];
-    // ---- implicit symmetric QR on (d, e) with deflation
+    // ---- implicit symmetric QR on (d, e) with deflation; rotations recorded
+    std::vector<Givens> rot;
     const double eps = 2.220446049250313e-16;
     auto negligible = [&](int i) { return std::fabs(e[i]) <= eps * (std::fabs(d[i]) + std::fabs(d[i + 1])); };
     int hi = n - 1, guard = 0;
@@ -229,19 +284,48 @@ void sym_eig_tridiag(int n, std::vector<double>& a, std::vector<double>& evals, 
                 e[k + 1] = c * e[k + 1];
                 x = e[k];
             }
-            double* rk = &vt[(size_t)k * n];
-            double* rk1 = &vt[(size_t)(k + 1) * n];
-            for (int j = 0; j < n; ++j) {
-                const double y0 = rk[j], y1 = rk1[j];
-                rk[j] = c * y0 - s * y1;
-                rk1[j] = s * y0 + c * y1;
-            }
+            rot.push_back(Givens{k, c, s});
         }
     }
-    evals = d;
+    // ---- V^T, one slice of columns per member in a compact local copy
+    // (row i of the slice at i * width); member t then writes rows j0..j1 of
+    // v, which are the slice's columns
     v.assign((size_t)n * n, 0.0);
-    for (int j = 0; j < n; ++j)
-        for (int k = 0; k < n; ++k) v[(size_t)k * n + j] = vt[(size_t)j * n + k];
+    run_team(T, [&](int t) {
+        const int j0 = (int)((long long)n * t / T), j1 = (int)((long long)n * (t + 1) / T);
+        const int wdt = j1 - j0;
+        if (wdt <= 0) return;
+        std::vector<double> sl((size_t)n * wdt, 0.0), u(wdt);
+        for (int j = j0; j < j1; ++j) sl[(size_t)j * wdt + (j - j0)] = 1.0;
+        for (int k = 0; k + 2 < n; ++k) {
+            if (betas[k] == 0.0) continue;
+            const int m = n - k - 1;
+            const double* hv = &hvs[(size_t)k * n + k + 1];
+            for (int j = 0; j < wdt; ++j) u[j] = 0.0;
+            for (int i = 0; i < m; ++i) {
+                const double* ri = &sl[(size_t)(k + 1 + i) * wdt];
+                const double vi = hv[i];
+                for (int j = 0; j < wdt; ++j) u[j] += vi * ri[j];
+            }
+            for (int i = 0; i < m; ++i) {
+                double* ri = &sl[(size_t)(k + 1 + i) * wdt];
+                const double f = betas[k] * hv[i];
+                for (int j = 0; j < wdt; ++j) ri[j] -= f * u[j];
+            }
+        }
+        for (const Givens& g : rot) {
+            double* rk = &sl[(size_t)g.k * wdt];
+            double* rk1 = &sl[(size_t)(g.k + 1) * wdt];
+            for (int j = 0; j < wdt; ++j) {
+                const double y0 = rk[j], y1 = rk1[j];
+                rk[j] = g.c * y0 - g.s * y1;
+                rk1[j] = g.s * y0 + g.c * y1;
+            }
+        }
+        for (int k = j0; k < j1; ++k)
+            for (int j = 0; j < n; ++j) v[(size_t)k * n + j] = sl[(size_t)j * wdt + (k - j0)];
+    });
+    evals = d;
 }
 
 // Widened bounds from a Lanczos tridiagonal (alpha[0..J), beta[0..J), beta[J-1]
