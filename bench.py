@@ -178,29 +178,60 @@ def other_workload(args, torch, ciq, workloads) -> int:
                                              "reference_iters": rinfo["iters"],
                                              "reference_converged": rinfo["converged"]}}
     elif args.workload == 4:
+        # 64 problems of uneven N in one batched call: the persistent FP32
+        # product walks every active problem's row blocks each iteration
         wl = workloads.workload(4)
         probs = [ciq.Problem(torch.from_numpy(q.x).to(dev), q.kernel, q.lengthscale, q.outputscale, q.noise)
                  for q in wl.problems]
         bs = [torch.from_numpy(q.b).to(dev) for q in wl.problems]
-        kw = dict(q=wl.q, max_iter=wl.max_iter, tol=wl.tol)
-        ciq.ciq_invsqrt_mvm_batched(probs[:2], bs[:2], **kw)            # warm-up
+        kw = dict(q=wl.q, max_iter=wl.max_iter, tol=wl.tol, seed=4001)
+        ciq.ciq_invsqrt_mvm_batched(probs, bs, **kw)                    # warm-up (and the tuner)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         outs, infos = ciq.ciq_invsqrt_mvm_batched(probs, bs, **kw)
         torch.cuda.synchronize()
         t_batch = time.perf_counter() - t0
-        log(f"workload 4 batched: {t_batch:.2f} s; 64 single calls ...")
+        _, pinfos = ciq.ciq_invsqrt_mvm_batched(probs, bs, profile=True, **kw)   # product timing
+        torch.cuda.synchronize()
+        ns = np.array([q.n for q in wl.problems], dtype=np.float64)
+        s16 = wl.problems[0].s
+        flops = float(np.sum(2.0 * ns * ns * s16 * np.array([i["iters"] for i in pinfos])))
+        prod_ms = pinfos[0]["mvm_ms"]
+        achieved = flops / (prod_ms * 1e-3) / 1e12
+        # reference rate: the same on-the-fly FP32 product on the largest problem alone
+        big = int(np.argmax(ns))
+        vbig = torch.randn(wl.problems[big].n, s16, device=dev)
+        for _ in range(2):
+            ciq.ciq_kernel_mvm(probs[big], vbig)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            ciq.ciq_kernel_mvm(probs[big], vbig)
+        e1.record()
+        torch.cuda.synchronize()
+        ref_ms = e0.elapsed_time(e1) / 10
+        ref_rate = 2.0 * ns[big] ** 2 * s16 / (ref_ms * 1e-3) / 1e12
+        log(f"workload 4 batched: {t_batch:.2f} s; product {achieved:.1f} TFLOP/s vs {ref_rate:.1f} single; "
+            f"64 single calls ...")
         t0 = time.perf_counter()
         singles = [ciq.ciq_invsqrt_mvm(pr, bb, **kw) for pr, bb in zip(probs, bs)]
         torch.cuda.synchronize()
         t_seq = time.perf_counter() - t0
         cols = sum(bb.shape[1] for bb in bs)
         gap = max(_rel(o, sgl[0])[0] for o, sgl in zip(outs, singles))
-        res = {"workload": wl.name, "problems": len(probs), "sum_n": int(sum(q.n for q in wl.problems)),
-               "s": wl.problems[0].s, "q": wl.q, "tol": wl.tol,
+        res = {"workload": wl.name, "problems": len(probs), "sum_n": int(ns.sum()), "s": s16, "q": wl.q,
+               "tol": wl.tol,
                "batched": {"columns_per_s": cols / t_batch, "seconds": t_batch,
                            "iters_max": max(i["iters"] for i in infos), "iters_min": min(i["iters"] for i in infos),
                            "all_converged": all(i["converged"] for i in infos)},
+               "product_roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["f32"],
+                                    "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS["f32"],
+                                    "kernel": "mvm_f32_kernel (persistent work queue)", "product_ms": prod_ms,
+                                    "algorithmic_flops": flops},
+               "load_balance_efficiency": achieved / ref_rate,
+               "load_balance_reference": (f"the same FP32 product on the largest problem alone (n = {int(ns[big])}, "
+                                          f"S = {s16}): {ref_rate:.1f} TFLOP/s"),
                "sequential_single_calls": {"columns_per_s": cols / t_seq, "seconds": t_seq},
                "max_rel_gap_batched_vs_single": gap}
     elif args.workload == 6:

@@ -64,7 +64,13 @@ extern "C" {
 
 #define CIQ_F64     0   /* double everywhere; FP64 entries, FP64 MFMA contraction    */
 #define CIQ_F32     1   /* float inputs/outputs; FP32 entries, FP32 MFMA contraction
-                           (FP64 running sums); FP64 Krylov vectors and scalars    */
+                           (FP64 running sums); FP64 Krylov vectors and scalars.
+                           With a resident K, K^{-1/2}B solves of at most 32
+                           columns contract the FP32 entries on the FP64 MFMA
+                           (no FP32 sums: the result is the rounded matrix's),
+                           wider ones keep FP32 sums of 16 columns; K^{1/2}B
+                           solves keep FP32 sums of 16 (<= 32 columns) or 64
+                           columns, which its final product with K damps      */
 #define CIQ_BF16X3  2   /* as CIQ_F32, but the entries and V are split into BF16
                            hi + scaled lo parts: K V ~ Kh Vh + 2^-8 (Kh Vl + Kl Vh)
                            on bf16 MFMA, FP32 accumulation (~1e-5 per product)   */
@@ -133,8 +139,10 @@ typedef struct ciq_opts {
                                   once) or FP16 hi/lo pairs (CIQ_F16X3, 4 bytes per
                                   entry) and stream them in every product instead of
                                   re-evaluating them; the buffer is allocated and
-                                  freed inside the call. CIQ_BF16X3 and the batched
-                                  call ignore this field.                        */
+                                  freed inside the call. The batched call (FP32)
+                                  keeps one such FP32 matrix per problem (their
+                                  total must fit the same way). CIQ_BF16X3
+                                  ignores this field.                            */
     int32_t cache_budget_mib;  /* CIQ_CACHE_AUTO: largest matrix kept, in MiB
                                   (0: half of the free device memory at the call) */
     int32_t graph;             /* 1: capture two msMINRES iterations (all their
@@ -180,6 +188,9 @@ typedef struct ciq_info {
     int32_t precond_rank;      /* pivots the preconditioner's factor took (<= R), 0
                                   without preconditioning                           */
     double precond_trace;      /* trace of o^2 k(X, X) - Lbar Lbar^T (0 without)    */
+    double setup_ms;           /* host wall time (ms) of the preconditioner's or the
+                                  posterior's factors, built before the Krylov runs
+                                  (0 when the call has neither)                     */
 } ciq_info;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -236,8 +247,9 @@ int ciq_kernel_mvm_noalloc(const ciq_problem* p, int dtype, const void* v, int s
  * entries are written once into a buffer allocated for this call, then the
  * product kernel runs once with the launch configuration a solve of this n
  * and s uses, and the buffer is freed. dtype: CIQ_F64 (FP64 entries, FP64
- * MFMA), CIQ_F32 (FP64 entries rounded once to FP32, FP32 MFMA, FP64 sums
- * across 64-column chunks), CIQ_F16X3 (FP64 entries split into FP16
+ * MFMA), CIQ_F32 (FP64 entries rounded once to FP32, FP32 MFMA, FP32 sums
+ * of 16 or 64 columns as a K^{1/2}B solve runs them, FP64 beyond), CIQ_F16X3
+ * (FP64 entries split into FP16
  * hi + 2^-11 lo, V split likewise after a per-column power-of-two scale,
  * three part products on FP16 MFMA); CIQ_BF16X3 is CIQ_ENOTSUP.
  *   v, s, ldv, y, ldy: as for ciq_kernel_mvm.
@@ -296,10 +308,19 @@ int ciq_backward(const ciq_problem* p, const ciq_opts* o, int mode, const double
 
 /*
  * K_p^{-1/2} B_p for nprob independent problems of uneven n_p and d_p in one
- * run: every iteration launches ONE kernel-product kernel that walks a work
- * list over all problems, one reduction, one scalar and one update kernel;
- * each problem has its own eigenvalue bounds, shifts, Lanczos and Givens state
- * and stops on its own. All problems share kernel type, dtype (CIQ_F32), s, q.
+ * run: every iteration launches ONE persistent kernel-product kernel (a grid
+ * of the blocks the device holds at once, taking (problem, row block, column
+ * range) items from a global counter, largest problem first, skipping
+ * problems that have stopped), then the inner-product, scalar and update
+ * kernels; with opts->graph the iteration's kernels are replayed from a HIP
+ * graph. The products stream one resident FP32 matrix per problem (FP64
+ * entries rounded once; ciq_opts.kernel_cache) or evaluate FP32 entries on
+ * the fly. Row tiles and column ranges per item are picked by the autotuner
+ * (see ciq_opts.kernel_cache's neighbours: the tuning cache file is
+ * $CIQ_TUNE_CACHE, else $HOME/.cache/libciq/tune.txt; empty disables it).
+ * Each problem has its own eigenvalue bounds, shifts, Lanczos and Givens
+ * state and stops on its own. All problems share kernel type, dtype
+ * (CIQ_F32), s, q.
  *   probs: host array [nprob]; b, out: host arrays [nprob] of device pointers
  *   (n_p x s, contiguous); infos: host array [nprob].
  * Synchronous. Errors as for ciq_invsqrt_mvm.
@@ -340,9 +361,13 @@ int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_ou
  * the caller's (not checked; a violation shows as non-convergence or
  * CIQ_ENUMERIC).
  *   a: host struct of device arrays; b, out: device n x s doubles.
- * Synchronous. Errors: CIQ_EINVAL (a, its arrays, n, mode, and the checks of
- * ciq_invsqrt_mvm); CIQ_ENOTSUP unless o->dtype == CIQ_F64 and
- * o->precond_rank == 0.
+ * Before any product the arrays' structure is checked on the device
+ * (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz, every col_idx in
+ * [0, n)); a malformed operator is CIQ_EINVAL. row_ptr must hold n + 1 and
+ * col_idx / val nnz entries (not checkable).
+ * Synchronous. Errors: CIQ_EINVAL (a, its arrays, n, mode, a malformed CSR
+ * structure, and the checks of ciq_invsqrt_mvm); CIQ_ENOTSUP unless
+ * o->dtype == CIQ_F64 and o->precond_rank == 0.
  */
 int ciq_csr_mvm(const ciq_csr* a, int mode, const ciq_opts* o, const double* b, int s, int ldb,
                 double* out, int ldo, ciq_info* info, hipStream_t stream);

@@ -86,6 +86,7 @@ class ciq_info(ctypes.Structure):
         ("kernel_cached", ctypes.c_int32),
         ("precond_rank", ctypes.c_int32),
         ("precond_trace", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -105,6 +106,7 @@ class ciq_info(ctypes.Structure):
             "kernel_cached": bool(self.kernel_cached),
             "precond_rank": self.precond_rank,
             "precond_trace": self.precond_trace,
+            "setup_ms": self.setup_ms,
         }
 
 

@@ -119,6 +119,8 @@ struct MvmArgs {
     int dp;
     int nsplit;
     int rt;                  // FP32 product: row tiles of 16 per wave (1 or 2)
+    int acc;                 // FP32 resident product: 1 = the finer FP64 accumulation
+                             // (inverse root), 0 = the faster one (see mvm_cache.hip)
     int ard;                 // FP32 product: per-dimension scales differ
     double scale[CIQ_MAX_D]; // FP32 product: per-dimension scale of coordinate differences
     const double* pscale;    // batched: [nprob][CIQ_MAX_D] scales
@@ -134,6 +136,10 @@ struct MvmArgs {
     const float* ps2;        // [nprob]
     const int* prob_done;    // [nprob] or nullptr
     const int* done;         // global done flag or nullptr
+    int* queue;              // batched FP32 products: persistent work counter (nullptr: one block per item)
+    int nitems;              // work items = nrb * nsplit
+    const long long* pkt;    // batched resident FP32: per-problem element offset of its matrix in kt
+    const long long* pnjs;   // per-problem padded columns / 4
     // resident kernel matrix (single problem): operand-tiled unit-scale
     // entries, double (CIQ_F64) or float (CIQ_F32), see mvm_cache.hip;
     // nullptr = evaluate entries on the fly
@@ -168,7 +174,7 @@ hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st);
 hipError_t launch_mvm_kt16(const MvmArgs& a, int nsb, hipStream_t st);
 // Blocks of the resident product (FP32 or FP64 operands, nsb column blocks of
 // 16, rt row tiles per wave) that one CU holds at once; 0 if the query fails.
-int kt_blocks_per_cu(int dtype, int nsb, int rt);
+int kt_blocks_per_cu(int dtype, int nsb, int rt, int acc = 0);
 // column blocks one product launch covers: 8 x 16 for the on-the-fly FP32
 // product and the resident split FP16 one, 4 x 16 otherwise
 inline int product_cap(int dtype, bool cached) {
@@ -297,6 +303,9 @@ struct SparseOp {
     const int* col;          // [nnz]
     const double* val;       // [nnz]
 };
+// *bad |= 1 unless row_ptr[0] = 0, row_ptr is non-decreasing, row_ptr[n] = nnz
+// and every col[k] lies in [0, n) (the caller zeroes *bad).
+hipError_t launch_csr_check(const int* row_ptr, const int* col, int n, int nnz, int* bad, hipStream_t st);
 // y = A x for s columns (x: n x s, ld ldx; y: n x s, ld ldy); `done` as above.
 hipError_t launch_spmv(const SparseOp& a, const double* x, int ldx, int s, double* y, int ldy, const int* done,
                        hipStream_t st);

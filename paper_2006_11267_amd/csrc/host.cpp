@@ -7,9 +7,14 @@
 // scalar Givens stage, fused vector update; all queued on the caller's
 // stream, optionally replayed from a HIP graph; the host polls a device
 // "done" flag every few iterations) -> combine.
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
+#include <string>
 #include <tuple>
 #include <cmath>
 #include <cstring>
@@ -121,18 +126,88 @@ int pad_dims(int d, int dtype) {
 
 // ---- kernel-product autotuner ---------------------------------------------
 // Candidates: RT (16-row tiles per wave, 1 or 2; register use vs operand
-// reuse) with the split of the j range that fills the chip for that RT. Each
-// candidate's product is timed with HIP events on the problem itself the
-// first time a (dtype, kernel, dims, column blocks, log2 N) key is met; the
-// winner is cached for the process.
+// reuse) with the split of the j range that fills the chip for that RT; for
+// batched runs also the number of column ranges per work item (1, 2, 4).
+// Each candidate's product is timed with HIP events on the problem itself the
+// first time a (device, dtype, kernel, dims, column blocks, log2 rows,
+// resident, problems, accumulation) key is met. Winners are kept for the
+// process and in a text file, one "key = rt nsplit" line each (lines that
+// do not parse are skipped): $CIQ_TUNE_CACHE if set (empty: no file), else
+// $HOME/.cache/libciq/tune.txt.
 struct TuneKey {
-    int dtype, kernel, dp, nsb, nlog, cached;
+    std::string arch;
+    int dtype, kernel, dp, nsb, nlog, cached, batched, acc;
     bool operator<(const TuneKey& o) const {
-        return std::tie(dtype, kernel, dp, nsb, nlog, cached) <
-               std::tie(o.dtype, o.kernel, o.dp, o.nsb, o.nlog, o.cached);
+        return std::tie(arch, dtype, kernel, dp, nsb, nlog, cached, batched, acc) <
+               std::tie(o.arch, o.dtype, o.kernel, o.dp, o.nsb, o.nlog, o.cached, o.batched, o.acc);
+    }
+    std::string text() const {
+        char b[256];
+        std::snprintf(b, sizeof(b), "%s %d %d %d %d %d %d %d %d", arch.c_str(), dtype, kernel, dp, nsb, nlog, cached,
+                      batched, acc);
+        return b;
     }
 };
-std::map<TuneKey, int> g_tuned_rt;   // guarded by the device scratch lock
+struct TuneVal {
+    int rt, nsplit;   // nsplit 0: the split rule of Run::configure
+};
+std::map<TuneKey, TuneVal> g_tuned;   // guarded by the device scratch lock
+bool g_tune_loaded = false;
+
+std::string tune_cache_path() {
+    const char* e = std::getenv("CIQ_TUNE_CACHE");
+    if (e) return std::string(e);
+    const char* h = std::getenv("HOME");
+    return h ? std::string(h) + "/.cache/libciq/tune.txt" : std::string();
+}
+
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    std::FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512], arch[128];
+    TuneKey k;
+    TuneVal v;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d = %d %d", arch, &k.dtype, &k.kernel, &k.dp, &k.nsb,
+                        &k.nlog, &k.cached, &k.batched, &k.acc, &v.rt, &v.nsplit) != 11)
+            continue;
+        k.arch = arch;
+        if (v.rt >= 1 && v.rt <= 2 && v.nsplit >= 0 && v.nsplit <= 8) g_tuned[k] = v;
+    }
+    std::fclose(f);
+}
+
+void tune_cache_store(const TuneKey& k, const TuneVal& v) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {   // create the directory chain (best effort)
+        for (size_t i = 1; i <= slash; ++i)
+            if (path[i] == '/' || i == slash) (void)::mkdir(path.substr(0, i == slash ? slash : i).c_str(), 0755);
+    }
+    std::FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s = %d %d\n", k.text().c_str(), v.rt, v.nsplit);
+    std::fclose(f);
+}
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    char b[160];
+    std::snprintf(b, sizeof(b), "%s/%dcu", prop.gcnArchName, prop.multiProcessorCount);
+    for (char* c = b; *c; ++c)
+        if (*c == ' ' || *c == '=') *c = '_';
+    return b;
+}
 
 bool valid_problem(const ciq_problem* p) {
     if (!p || !p->x || !p->lengthscale) return false;
@@ -452,7 +527,12 @@ struct Run {
     double tol = 0.0;
     int bounds_mode = 0;
     int nsplit = 1, nrb = 0, rt = 2, nsplit_alloc = 1, nrb_alloc = 1;
+    int nsplit_fixed = 0;    // batched: column ranges per work item chosen by the tuner (0: the rule below)
+    int* queue = nullptr;    // batched FP32: persistent product's work counter
+    long long* pkt = nullptr;    // batched resident FP32: per-problem matrix offsets (elements)
+    long long* pnjs = nullptr;   // per-problem padded columns / 4
     bool keep_solves = false;
+    int fine_acc = 0;      // FP32 resident products: the finer FP64 accumulation (inverse root)
     bool cached = false;   // products stream a resident kernel matrix (kt)
     bool precond = false;  // preconditioned run (single problem): Lanczos in the P^{-1} inner product
     const Precond* pc = nullptr;
@@ -493,6 +573,7 @@ struct Run {
     std::vector<float> h_o2, h_s2;
     std::vector<double> h_scale;
     std::vector<double> h_o2d, h_s2d;
+    std::vector<long long> h_pkt, h_pnjs;
     int ard = 0;
 
     template <typename A>
@@ -522,6 +603,9 @@ struct Run {
             pbuf[1] = a.template take<double>(vec);
         }
         wl = a.template take<WorkItem>(std::max(nrb_alloc, 1));
+        queue = a.template take<int>(1);
+        pkt = a.template take<long long>(nprob);
+        pnjs = a.template take<long long>(nprob);
         pn = a.template take<int>(nprob);
         poff = a.template take<int>(nprob);
         po2 = a.template take<float>(nprob);
@@ -581,7 +665,7 @@ struct Run {
             // one more N x S FP64 write and read, ~0.2 % of a product); at
             // most 2, so the V slices an XCD streams stay within its L2
             const int nsb = (std::min(s, product_cap(dtype, true)) + 15) / 16;
-            const int bpc = kt_blocks_per_cu(dtype, nsb, rt);
+            const int bpc = kt_blocks_per_cu(dtype, nsb, rt, fine_acc);
             int m = 1;
             if (bpc > 0) {
                 const double slots = 32.0 * bpc;
@@ -595,6 +679,7 @@ struct Run {
         } else if (cached && (max_n + 63) / 64 >= 8 && nrb * 8 >= 512) {
             nsplit = 8;   // one column range per XCD
         }
+        if (nprob > 1 && nsplit_fixed > 0) nsplit = nsplit_fixed;
         if (sp || dn) nsplit = 1;   // the sparse / dense products write one partial
         ysplit = (long long)rows_total * s;
     }
@@ -608,6 +693,7 @@ struct Run {
             nsplit_alloc = std::max(nsplit_alloc, nsplit);
             nrb_alloc = std::max(nrb_alloc, nrb);
         }
+        if (nprob > 1) nsplit_alloc = std::max(nsplit_alloc, 4);   // the tuner's batched candidates
         configure(rt_);
     }
 
@@ -627,10 +713,16 @@ struct Run {
         d.bounds_mode = bounds_mode;
     }
 
+    // Work list: every problem's row blocks, largest problem first (its items
+    // cost the most; the persistent product takes them in list order, so the
+    // small items fill the end of the launch).
     int upload_tables(hipStream_t st) {
         const int rpb = rows_per_block();
+        std::vector<int> order(nprob);
+        for (int p = 0; p < nprob; ++p) order[p] = p;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return h_n[x] > h_n[y]; });
         std::vector<WorkItem> h_wl;
-        for (int p = 0; p < nprob; ++p) {
+        for (int p : order) {
             const int nb = (h_n[p] + rpb - 1) / rpb;
             for (int r = 0; r < nb; ++r) h_wl.push_back(WorkItem{p, r});
         }
@@ -640,6 +732,8 @@ struct Run {
         HIPCHK(hipMemcpyAsync(po2, h_o2.data(), nprob * sizeof(float), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(ps2, h_s2.data(), nprob * sizeof(float), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(pscale, h_scale.data(), h_scale.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pkt, h_pkt.data(), nprob * sizeof(long long), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pnjs, h_pnjs.data(), nprob * sizeof(long long), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));  // host vectors are pageable and short-lived
         return CIQ_OK;
     }
@@ -657,6 +751,7 @@ struct Run {
         a.dp = dp;
         a.nsplit = nsplit;
         a.rt = rt;
+        a.acc = fine_acc;
         a.ard = ard;
         for (int k = 0; k < CIQ_MAX_D; ++k) a.scale[k] = h_scale[k];
         a.pscale = pscale;
@@ -671,6 +766,10 @@ struct Run {
         a.ps2 = ps2;
         a.prob_done = (nprob > 1) ? d.prob_done : nullptr;
         a.done = &d.st->done;
+        a.queue = (nprob > 1 && dtype == CIQ_F32) ? queue : nullptr;
+        a.nitems = nrb * nsplit;
+        a.pkt = (nprob > 1) ? pkt : nullptr;
+        a.pnjs = (nprob > 1) ? pnjs : nullptr;
         a.kt = kt;
         a.njs = njs;
         a.vt = vt16;
@@ -863,8 +962,9 @@ struct Run {
     // the combined solution lives in acc, the per-shift solves in `solves`.
 };
 
-// Pick RT for this run (see TuneKey). `operand` holds any n x s data in the
-// product's input type; the timed launches write only the partial buffer.
+// Pick RT (and for batched runs the column ranges per item) for this run
+// (see TuneKey). `operand` holds any n x s data in the product's input type;
+// the timed launches write only the partial buffer.
 template <typename T>
 int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
     if (r.sp || r.dn) {
@@ -872,26 +972,38 @@ int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
         return CIQ_OK;
     }
     const int nsb = (std::min(r.s, product_cap(r.dtype, r.cached)) + 15) / 16;
+    const bool batched = r.nprob > 1;
     // one row tile per wave: the widest FP32 on-the-fly and split FP16 resident
     // launches (register budget) and the on-the-fly split forms
-    if ((r.dtype == CIQ_F32 && nsb >= 8) || (r.dtype == CIQ_F16X3 && r.cached && nsb > 4) ||
-        r.dtype == CIQ_BF16X3 || (r.dtype == CIQ_F16X3 && !r.cached)) {
+    const bool rt1 = (r.dtype == CIQ_F32 && nsb >= 8) || (r.dtype == CIQ_F16X3 && r.cached && nsb > 4) ||
+                     r.dtype == CIQ_BF16X3 || (r.dtype == CIQ_F16X3 && !r.cached);
+    if (rt1 && !batched) {
         r.configure(1);
-        return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
+        return CIQ_OK;
     }
     int nlog = 0;
     while ((1 << (nlog + 1)) <= r.rows_total) ++nlog;
-    const TuneKey key{r.dtype, r.kernel, r.dp, nsb, nlog, r.cached ? 1 : 0};
-    auto it = g_tuned_rt.find(key);
-    if (it == g_tuned_rt.end()) {
+    tune_cache_load();
+    const TuneKey key{device_arch(), r.dtype, r.kernel, r.dp, nsb, nlog, r.cached ? 1 : 0, batched ? 1 : 0,
+                      r.fine_acc};
+    auto it = g_tuned.find(key);
+    if (it == g_tuned.end()) {
+        std::vector<TuneVal> cands;
+        for (int rt = 1; rt <= (rt1 ? 1 : 2); ++rt) {
+            if (batched)
+                for (int ns : {1, 2, 4}) cands.push_back(TuneVal{rt, ns});
+            else
+                cands.push_back(TuneVal{rt, 0});
+        }
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         float best_ms = 1e30f;
-        int best = 2;
-        for (int cand = 1; cand <= 2; ++cand) {
-            r.configure(cand);
-            if (r.nprob > 1) STCHK(r.upload_tables(st));
+        TuneVal best = cands.back();
+        for (const TuneVal& c : cands) {
+            r.nsplit_fixed = c.nsplit;
+            r.configure(c.rt);
+            if (batched) STCHK(r.upload_tables(st));
             MvmArgs a = r.mvm_args(operand, r.ypart);
             a.done = nullptr;
             a.prob_done = nullptr;
@@ -904,15 +1016,17 @@ int tune_rt(Run<T>& r, const void* operand, hipStream_t st) {
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best_ms) {
                 best_ms = ms;
-                best = cand;
+                best = c;
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        it = g_tuned_rt.emplace(key, best).first;
+        it = g_tuned.emplace(key, best).first;
+        tune_cache_store(key, best);
     }
-    r.configure(it->second);
-    return r.nprob > 1 ? r.upload_tables(st) : CIQ_OK;
+    r.nsplit_fixed = it->second.nsplit;
+    r.configure(it->second.rt);
+    return batched ? r.upload_tables(st) : CIQ_OK;
 }
 
 template <typename T>
@@ -961,6 +1075,15 @@ void fill_problem_tables(Run<T>& r, const ciq_problem* probs, int nprob, int dty
     }
     r.rows_total = off;
     r.max_n = maxn;
+    // resident matrices one after another (FP32 elements), each in its own padded layout
+    r.h_pkt.resize(nprob);
+    r.h_pnjs.resize(nprob);
+    long long kofs = 0;
+    for (int p = 0; p < nprob; ++p) {
+        r.h_pkt[p] = kofs;
+        r.h_pnjs[p] = (long long)(kcache_cols(probs[p].n) / 4);
+        kofs += (long long)(kcache_rows(probs[p].n) * kcache_cols(probs[p].n));
+    }
     r.dp = pad_dims(maxd, r.dtype);
     r.kernel = probs[0].kernel;
 }
@@ -981,11 +1104,12 @@ struct KCache {
 // Whether (and then where) a solve keeps K resident; CIQ_OK with *out = nullptr
 // means the products evaluate entries on the fly.
 int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* probs, KCache& kc) {
-    if ((dtype != CIQ_F64 && dtype != CIQ_F32 && dtype != CIQ_F16X3) || nprob != 1 ||
-        o->kernel_cache == CIQ_CACHE_OFF)
+    if ((dtype != CIQ_F64 && dtype != CIQ_F32 && dtype != CIQ_F16X3) || o->kernel_cache == CIQ_CACHE_OFF)
         return CIQ_OK;
+    if (nprob != 1 && dtype != CIQ_F32) return CIQ_OK;   // batched: FP32 matrices, one per problem
     kc.elem = (dtype == CIQ_F64) ? 8 : 4;    // FP32, or the FP16 hi + lo pair
-    const size_t bytes = kcache_bytes(probs[0].n, kc.elem);
+    size_t bytes = 0;
+    for (int p = 0; p < nprob; ++p) bytes += kcache_bytes(probs[p].n, kc.elem);
     if (o->kernel_cache != CIQ_CACHE_ON) {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
@@ -1006,6 +1130,27 @@ int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* p
 template <typename T>
 int kcache_build(Run<T>& r, const KCache& kc, hipStream_t st) {
     if (!kc.ptr) return CIQ_OK;
+    if (r.nprob > 1) {   // one FP32 matrix per problem, entries in FP64 rounded once
+        for (int p = 0; p < r.nprob; ++p) {
+            KBuildArgs ka{};
+            ka.xh = r.xh + (size_t)r.h_off[p] * r.dp;
+            ka.ard = 0;
+            for (int k = 0; k < CIQ_MAX_D; ++k) {
+                ka.scale[k] = r.h_scale[(size_t)p * CIQ_MAX_D + k];
+                if (ka.scale[k] != ka.scale[0] && ka.scale[k] != 0.0) ka.ard = 1;
+            }
+            ka.n = r.h_n[p];
+            ka.dp = r.dp;
+            ka.kernel = r.kernel;
+            ka.nchunk = (int)(kcache_cols(ka.n) / 64);
+            ka.njs = (long long)(kcache_cols(ka.n) / 4);
+            ka.elem = 1;
+            ka.kt = static_cast<float*>(kc.ptr) + r.h_pkt[p];
+            HIPCHK(launch_kbuild(ka, st));
+        }
+        r.kt = kc.ptr;
+        return CIQ_OK;
+    }
     KBuildArgs ka{};
     ka.xh = r.xh;
     for (int k = 0; k < CIQ_MAX_D; ++k) ka.scale[k] = r.h_scale[k];
@@ -1064,6 +1209,9 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     main.max_iter = o->max_iter;
     main.tol = o->tol;
     main.keep_solves = (solves_out != nullptr);
+    // the inverse root amplifies the products' FP32 rounding in the
+    // noise-level eigendirections; the square root's final K damps it
+    main.fine_acc = (mode != CIQ_SQRT) ? 1 : 0;
     main.plan(2);
 
     Run<T> bnd;
@@ -1105,6 +1253,10 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     STCHK(kcache_build(main, kc, st));
     bnd.kt = main.kt;
     bnd.njs = main.njs;
+    // the point and matrix set-up above is queued work: finish it first so
+    // the factors' build time is their own
+    if (precond || post_spec) HIPCHK(hipStreamSynchronize(st));
+    const auto setup_t0 = std::chrono::steady_clock::now();
     if (precond) {
         STCHK(pc_build(probs[0], main.xh, main.dp, main.kernel, main.ard, main.h_scale.data(), o->precond_rank, s,
                        pc, st));
@@ -1122,6 +1274,10 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         main.post = &po;
         bnd.post = &po;
     }
+    // both builds end synchronised with the stream
+    const double setup_ms = (precond || post_spec)
+        ? std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - setup_t0).count()
+        : 0.0;
 
     std::vector<double> lmin(nprob), lmax(nprob);
     int mvm_count = 0;
@@ -1289,6 +1445,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         in.kernel_cached = (kc.ptr != nullptr) ? 1 : 0;
         in.precond_rank = precond ? pc.rank : 0;
         in.precond_trace = precond ? pc.trace : 0.0;
+        in.setup_ms = setup_ms;
     }
     return CIQ_OK;
 }
@@ -1333,6 +1490,7 @@ int backward_impl(const ciq_problem* p, const ciq_opts* o, int mode, const doubl
     r.max_iter = o->max_iter;
     r.tol = o->tol;
     r.keep_solves = true;
+    r.fine_acc = sqrt_mode ? 0 : 1;
     r.cached = (kc.ptr != nullptr);
     r.plan(2);
 
@@ -1780,6 +1938,20 @@ int ciq_csr_mvm(const ciq_csr* a, int mode, const ciq_opts* o, const double* b, 
     const int rc = check_solve_args(&p, o, b, s, ldb, out, ldo, info);
     if (rc != CIQ_OK) return rc;
     if (o->dtype != CIQ_F64 || o->precond_rank != 0) return CIQ_ENOTSUP;
+    {   // the structure of the caller's CSR arrays, before any product reads them
+        int dev;
+        STCHK(get_device(&dev));
+        ScratchLock lock(dev);
+        void* base = nullptr;
+        STCHK(scratch_reserve(dev, 4096, &base));
+        int* bad = static_cast<int*>(base);
+        HIPCHK(launch_fill<int>(bad, 1, 0, stream));
+        HIPCHK(launch_csr_check(a->row_ptr, a->col_idx, a->n, a->nnz, bad, stream));
+        int h_bad = 0;
+        HIPCHK(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (h_bad) return CIQ_EINVAL;
+    }
     const SparseOp sp{a->n, a->row_ptr, a->col_idx, a->val};
     const void* bp[1] = {b};
     void* op[1] = {out};

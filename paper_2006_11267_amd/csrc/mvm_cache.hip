@@ -302,23 +302,42 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt_kernel(MvmArgs a) {
 }
 
 // FP32 resident matrix (CIQ_F32): the same structure with FP32 operands and
-// MFMA, FP32 accumulation per 64-column chunk and FP64 across chunks.
-template <int NSB, int RT, int WAVES, int KD>
-__global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
+// MFMA, FP32 sums inside a 64-column chunk and FP64 across chunks. The FP32
+// sums are the rounding that limits ill-conditioned problems: every product
+// adds fresh noise of about 2^-24 |running FP32 sum| per MFMA, which lands
+// in the noise-level eigendirections that the inverse root amplifies, and
+// it grows as the square root of the MFMA steps B one FP32 sum spans.
+// NACC picks B: NACC accumulators take the chunk's 16 steps in rotation
+// (B = 16 / NACC, NACC = 1 or 4), and NACC = 0 takes each MFMA's output
+// into FP64 at once (B = 1, four converts and adds per MFMA). NACC = -1
+// contracts on the FP64 MFMA instead, the FP32 operands converted as they
+// are used (two converts per MFMA, no FP32 sums at all): at half the FP32
+// MFMA rate, which launches of at most 32 columns can afford, since they
+// stream K at HBM speed with the matrix cores less than half busy. Those
+// launches use B = 4, or the FP64 MFMA for the inverse root (a.acc); the
+// 64-column launch is MFMA-bound and uses B = 16, or B = 4 for the inverse
+// root.
+// Batched runs (a.wl set) keep one such matrix per problem (a.pkt: its
+// element offset, a.pnjs: its padded columns / 4) and run persistently: a
+// grid of the resident blocks takes (problem, row block, column range) items
+// from the global counter a.queue in list order (largest problem first),
+// skipping problems that have stopped.
+template <int NSB, int RT, int WAVES, int KD, int NACC>
+__device__ __forceinline__ void kt32_item(const MvmArgs& a, int p, int rb, int split, float* vs) {
     constexpr int NT = 64 * WAVES;
     constexpr int BN = 64;
     constexpr int S16 = NSB * 16;
     constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
-    __shared__ __attribute__((aligned(16))) float vs[BN * VST];
 
-    if (mfma::done_now(a.done)) return;
     const int nsplit = a.nsplit;
-    const int split = (int)(blockIdx.x % (unsigned)nsplit);
-    const int rb = (int)(blockIdx.x / (unsigned)nsplit);
-    const int n = a.n;
-    const double o2 = a.o2, s2 = a.s2;
-    const float* __restrict__ v = static_cast<const float*>(a.v);
-    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    const int n = (p < 0) ? a.n : a.pn[p];
+    const long long off = (p < 0) ? 0 : a.poff[p];
+    const long long njs = (p < 0) ? a.njs : a.pnjs[p];
+    const float* kt = static_cast<const float*>(a.kt) + ((p < 0) ? 0 : a.pkt[p]);
+    const double o2 = (p < 0) ? a.o2 : (double)a.po2[p];
+    const double s2 = (p < 0) ? a.s2 : (double)a.ps2[p];
+    const float* __restrict__ v = static_cast<const float*>(a.v) + off * a.ldv;
+    double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit + off * a.ldy;
     const int s = a.s, ldv = a.ldv, ldy = a.ldy;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -330,16 +349,25 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
     const int c0 = (int)(((long long)split * nchunk) / nsplit);
     const int c1 = (int)(((long long)(split + 1) * nchunk) / nsplit);
 
-    // FP32 accumulation within a chunk, FP64 across chunks
-    floatx4 acc[RT][NSB];
+    // FP32 sums of B = 16 / NACC steps (NACC = 0: one step), FP64 beyond;
+    // NACC = -1: FP64 MFMA, in two chains when the wave has one output tile
+    static_assert(NACC >= -1 && NACC <= 4 && NACC != 3, "accumulator rotation");
+    constexpr bool F64M = NACC < 0;
+    constexpr int NA = NACC > 0 ? NACC : 1;
+    constexpr int NC = (F64M && RT * NSB == 1) ? 2 : 1;
+    floatx4 acc[NA][RT][NSB];
     double accd[RT][NSB][4];
+    doublex4 acc64[NC][RT][NSB];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int sb = 0; sb < NSB; ++sb) {
-            acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int h = 0; h < NA; ++h) acc[h][rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
+#pragma unroll
+            for (int h = 0; h < NC; ++h) acc64[h][rt][sb] = doublex4{0.0, 0.0, 0.0, 0.0};
         }
 
     // thread (vr, vc) moves 4 consecutive columns vc*4.. of rows vr + k * VR:
@@ -375,7 +403,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
     // operand loads: uniform base per (16-row tile, chunk), lane offset l + 64 st
     const float* kb[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) kb[rt] = static_cast<const float*>(a.kt) + (size_t)(tile0 + rt) * a.njs * 64;
+    for (int rt = 0; rt < RT; ++rt) kb[rt] = kt + (size_t)(tile0 + rt) * njs * 64;
     // KD chunks of operands in flight: chunk c + KD - 1 is requested while c
     // is contracted
     float kq[KD][RT][16];
@@ -410,22 +438,46 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
 #pragma unroll
                 for (int sb = 0; sb < NSB; ++sb) bnxt[sb] = vs[jn * VST + sb * 16 + (lane & 15)];
             }
+            if constexpr (F64M) {
 #pragma unroll
-            for (int sb = 0; sb < NSB; ++sb)
+                for (int sb = 0; sb < NSB; ++sb)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-                    acc[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[rt][st], bcur[sb], acc[rt][sb], 0, 0, 0);
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc64[st % NC][rt][sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            (double)cur[rt][st], (double)bcur[sb], acc64[st % NC][rt][sb], 0, 0, 0);
+            } else if constexpr (NACC == 0) {
+#pragma unroll
+                for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) {
+                        const floatx4 t = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            cur[rt][st], bcur[sb], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)t[r];
+                    }
+            } else {
+#pragma unroll
+                for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[st % NA][rt][sb] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(cur[rt][st], bcur[sb], acc[st % NA][rt][sb], 0, 0, 0);
+            }
 #pragma unroll
             for (int sb = 0; sb < NSB; ++sb) bcur[sb] = bnxt[sb];
         }
+        if constexpr (NACC > 0) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+            for (int h = 0; h < NA; ++h)
 #pragma unroll
-            for (int sb = 0; sb < NSB; ++sb) {
+                for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[rt][sb][r];
-                acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
+                    for (int sb = 0; sb < NSB; ++sb) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[h][rt][sb][r];
+                        acc[h][rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    }
+        }
     };
     if (c0 < c1) fetch_v(c0);
 #pragma unroll
@@ -445,15 +497,46 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
             const int cc = sb * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = row0 + rt * 16 + 4 * (lane >> 4) + r;   // FP32 16x16x4 layout
+                // FP32 16x16x4 layout: row 4 (lane / 16) + r; FP64: lane / 16 + 4 r
+                const int i = row0 + rt * 16 + (F64M ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
                 if (i < n && cc < s) {
-                    double val = o2 * accd[rt][sb][r];
+                    double sum = accd[rt][sb][r];
+                    if constexpr (F64M) {
+                        sum = acc64[0][rt][sb][r];
+#pragma unroll
+                        for (int h = 1; h < NC; ++h) sum += acc64[h][rt][sb][r];
+                    }
+                    double val = o2 * sum;
                     if (split == 0) val = fma(s2, (double)v[(long long)i * ldv + cc], val);
                     y[(long long)i * ldy + cc] = val;
                 }
             }
         }
     }
+}
+
+template <int NSB, int RT, int WAVES, int KD, int NACC>
+__global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
+    constexpr int S16 = NSB * 16;
+    constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
+    __shared__ __attribute__((aligned(16))) float vs[64 * VST];
+    __shared__ int item_sh;
+    if (mfma::done_now(a.done)) return;
+    if (a.queue != nullptr) {            // batched, persistent
+        for (;;) {
+            __syncthreads();             // every thread has read the previous item
+            if (threadIdx.x == 0) item_sh = atomicAdd(a.queue, 1);
+            __syncthreads();
+            const int item = item_sh;
+            if (item >= a.nitems) break;
+            const WorkItem wi = a.wl[item / a.nsplit];
+            if (a.prob_done != nullptr && a.prob_done[wi.prob]) continue;
+            kt32_item<NSB, RT, WAVES, KD, NACC>(a, wi.prob, wi.rb, item % a.nsplit, vs);
+        }
+        return;
+    }
+    kt32_item<NSB, RT, WAVES, KD, NACC>(a, -1, (int)(blockIdx.x / (unsigned)a.nsplit),
+                                  (int)(blockIdx.x % (unsigned)a.nsplit), vs);
 }
 
 // Split FP16 resident matrix (CIQ_F16X3): the same block structure; per
@@ -618,13 +701,52 @@ hipError_t launch_kbuild(const KBuildArgs& a, hipStream_t st) {
                  : launch_kbuild_t<CIQ_KERNEL_MATERN52, false>(a, grid, st);
 }
 
+template <typename K>
+static int occupancy_of(K kernel, int threads = 256) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+// accumulator rotation of a launch (see kt32_item)
+constexpr int kt32_nacc(int nsb, int acc) { return nsb <= 2 ? (acc ? -1 : 4) : (acc ? 4 : 1); }
+
+template <int NSB, int RT, int NACC>
+hipError_t launch_kt32_variant(const MvmArgs& a, int grid, hipStream_t st) {
+    if (a.queue != nullptr) {            // batched: persistent grid of the resident blocks
+        static int slots = 0;
+        if (slots == 0) {
+            int dev = 0, ncu = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+                slots = std::max(1, occupancy_of(mvm_kt32_kernel<NSB, RT, 4, 2, NACC>)) * ncu;
+            else
+                slots = 1024;
+            (void)hipGetLastError();
+        }
+        const hipError_t e = launch_fill<int>(a.queue, 1, 0, st);
+        if (e != hipSuccess) return e;
+        grid = std::min(a.nitems, slots);
+    }
+    hipLaunchKernelGGL((mvm_kt32_kernel<NSB, RT, 4, 2, NACC>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int NSB>
 hipError_t launch_kt32_nsb(const MvmArgs& a, int grid, hipStream_t st) {
+    constexpr int fast = kt32_nacc(NSB, 0), fine = kt32_nacc(NSB, 1);
     if (a.rt == 1)
-        hipLaunchKernelGGL((mvm_kt32_kernel<NSB, 1, 4, 2>), dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((mvm_kt32_kernel<NSB, 2, 4, 2>), dim3(grid), dim3(256), 0, st, a);
-    return hipGetLastError();
+        return a.acc ? launch_kt32_variant<NSB, 1, fine>(a, grid, st) : launch_kt32_variant<NSB, 1, fast>(a, grid, st);
+    return a.acc ? launch_kt32_variant<NSB, 2, fine>(a, grid, st) : launch_kt32_variant<NSB, 2, fast>(a, grid, st);
+}
+
+template <int NSB, int RT>
+int kt32_occupancy(int acc) {
+    return acc ? occupancy_of(mvm_kt32_kernel<NSB, RT, 4, 2, kt32_nacc(NSB, 1)>)
+               : occupancy_of(mvm_kt32_kernel<NSB, RT, 4, 2, kt32_nacc(NSB, 0)>);
 }
 
 // the row blocks of a launch must stay inside the padded rows of the matrix
@@ -643,15 +765,6 @@ hipError_t launch_mvm_kt(const MvmArgs& a, int nsb, hipStream_t st) {
     }
 }
 
-template <typename K>
-static int occupancy_of(K kernel, int threads = 256) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return nb;
-}
 
 // rt = 1: 64-row blocks of four one-tile waves; rt = 2: 128-row blocks, as
 // eight one-tile waves (one column block: four two-tile waves)
@@ -666,7 +779,7 @@ hipError_t launch_kt16_nsb(const MvmArgs& a, int grid, hipStream_t st) {
     return hipGetLastError();
 }
 
-int kt_blocks_per_cu(int dtype, int nsb, int rt) {
+int kt_blocks_per_cu(int dtype, int nsb, int rt, int acc) {
     const int k = nsb <= 1 ? 1 : (nsb <= 2 ? 2 : 4);
     if (dtype == CIQ_F16X3) {
         if (nsb > 4) return occupancy_of(mvm_kt16_kernel<8, 1, 4, 2>);
@@ -680,10 +793,8 @@ int kt_blocks_per_cu(int dtype, int nsb, int rt) {
     const bool f32 = (dtype == CIQ_F32);
     if (f32) {
         if (rt == 1)
-            return k == 1 ? occupancy_of(mvm_kt32_kernel<1, 1, 4, 2>)
-                          : (k == 2 ? occupancy_of(mvm_kt32_kernel<2, 1, 4, 2>) : occupancy_of(mvm_kt32_kernel<4, 1, 4, 2>));
-        return k == 1 ? occupancy_of(mvm_kt32_kernel<1, 2, 4, 2>)
-                      : (k == 2 ? occupancy_of(mvm_kt32_kernel<2, 2, 4, 2>) : occupancy_of(mvm_kt32_kernel<4, 2, 4, 2>));
+            return k == 1 ? kt32_occupancy<1, 1>(acc) : (k == 2 ? kt32_occupancy<2, 1>(acc) : kt32_occupancy<4, 1>(acc));
+        return k == 1 ? kt32_occupancy<1, 2>(acc) : (k == 2 ? kt32_occupancy<2, 2>(acc) : kt32_occupancy<4, 2>(acc));
     }
     if (rt == 1)
         return k == 1 ? occupancy_of(mvm_kt_kernel<1, 1, 4, 2>)
@@ -693,7 +804,8 @@ int kt_blocks_per_cu(int dtype, int nsb, int rt) {
 }
 
 hipError_t launch_mvm_kt32(const MvmArgs& a, int nsb, hipStream_t st) {
-    if (!kt_rows_ok(a)) return hipErrorInvalidValue;
+    if (a.wl == nullptr ? !kt_rows_ok(a) : (a.queue == nullptr || a.pkt == nullptr || a.pnjs == nullptr))
+        return hipErrorInvalidValue;
     const int grid = a.nrb * a.nsplit;
     switch (nsb) {
         case 1: return launch_kt32_nsb<1>(a, grid, st);

@@ -6,6 +6,8 @@
 
 #include "ciq_internal.h"
 
+#include <algorithm>
+
 namespace ciq {
 namespace mfma {
 
@@ -99,6 +101,13 @@ __device__ __forceinline__ double kentry64(double r2) {
 // B = V[j0 + 4*st + l/16][c0 + l%16] (from LDS); the accumulator holds
 // Y[i0 + 4*(l/16) + r][c0 + l%16], r = 0..3.
 //
+// Batched runs (a.wl set): with a.queue the kernel is persistent -- a grid of
+// the resident blocks, each taking work items (problem, row block, column
+// range) from a global counter in list order (the host orders the list by
+// problem size, largest first) until the list is exhausted; items of
+// problems that have stopped are skipped. Without a.queue, block
+// (x, y) does item (a.wl[x], split y).
+//
 // Accumulation: the MFMA accumulates one staged chunk of BN columns of K in
 // FP32; each lane then adds its chunk sums into FP64 registers and restarts
 // the FP32 accumulator. A plain FP32 accumulation over all N/nsplit columns
@@ -107,7 +116,7 @@ __device__ __forceinline__ double kentry64(double r2) {
 // of the FP32 kernel entries and of short FP32 chunk sums.
 // ----------------------------------------------------------------------------
 template <int KERNEL, int DP, int NSB, int RT, bool ARD>
-__global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
+__device__ __forceinline__ void mvm_f32_item(const MvmArgs& a, const WorkItem* wip, int split, float* xs, float* vs) {
     constexpr int BM = 64 * RT;
     constexpr int BN = 64;
     constexpr int S16 = NSB * 16;
@@ -116,16 +125,12 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     constexpr int XPT = (XE + 255) / 256;             // per thread
     constexpr int VPT = BN * S16 / 256;               // staged V floats per thread
     constexpr int VROWS = 256 / S16;                  // V rows covered by one pass of the block
-    __shared__ float xs[XE];
-    __shared__ float vs[BN * VST];
 
-    if (done_now(a.done)) return;
     int n, off, rb;
     double o2, s2;
     float sc[DP];     // per-dimension scale applied to coordinate differences
-    if (a.wl != nullptr) {
-        const WorkItem wi = a.wl[blockIdx.x];
-        if (a.prob_done != nullptr && a.prob_done[wi.prob]) return;
+    if (wip != nullptr) {
+        const WorkItem wi = *wip;
         n = a.pn[wi.prob];
         off = a.poff[wi.prob];
         rb = wi.rb;
@@ -144,7 +149,6 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     }
     // isotropic: r^2 = sc0^2 * sum_d (x_d - x'_d)^2 (one multiply per entry)
     const float sc0sq = sc[0] * sc[0];
-    const int split = blockIdx.y;
     const double* __restrict__ xh = static_cast<const double*>(a.xh) + (long long)off * DP;
     const float* __restrict__ v = static_cast<const float*>(a.v) + (long long)off * a.ldv;
     double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit + (long long)off * a.ldy;
@@ -163,13 +167,17 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
         for (int k = 0; k < DP; ++k) xi[rt][k] = (i < n) ? (float)xh[(long long)i * DP + k] : 0.0f;
     }
 
-    floatx4 acc[RT][NSB];
+    // narrow launches (<= 32 columns) rotate four FP32 accumulators over the
+    // chunk's 4-column steps: each FP32 sum spans 16 columns, not 64
+    constexpr int NACC = (NSB <= 2) ? 4 : 1;
+    floatx4 acc[NACC][RT][NSB];
     double accd[RT][NSB][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int sb = 0; sb < NSB; ++sb) {
-            acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int h = 0; h < NACC; ++h) acc[h][rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) accd[rt][sb][r] = 0.0;
         }
@@ -243,18 +251,21 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
                     const float bv = vs[jl * VST + sb * 16 + (lane & 15)];
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt)
-                        acc[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[rt], bv, acc[rt][sb], 0, 0, 0);
+                        acc[st % NACC][rt][sb] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(kv[rt], bv, acc[st % NACC][rt][sb], 0, 0, 0);
                 }
             }
         }
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+        for (int h = 0; h < NACC; ++h)
 #pragma unroll
-            for (int sb = 0; sb < NSB; ++sb) {
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[rt][sb][r];
-                acc[rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
+                for (int sb = 0; sb < NSB; ++sb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) accd[rt][sb][r] += (double)acc[h][rt][sb][r];
+                    acc[h][rt][sb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
     }
 
 #pragma unroll
@@ -275,18 +286,75 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
     }
 }
 
+template <int KERNEL, int DP, int NSB, int RT, bool ARD>
+__global__ __launch_bounds__(256) void mvm_f32_kernel(MvmArgs a) {
+    constexpr int S16 = NSB * 16;
+    constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
+    __shared__ float xs[64 * DP];
+    __shared__ float vs[64 * VST];
+    __shared__ int item_sh;
+    if (done_now(a.done)) return;
+    if (a.queue != nullptr) {           // persistent: items from the global counter
+        for (;;) {
+            __syncthreads();            // every thread has read the previous item
+            if (threadIdx.x == 0) item_sh = atomicAdd(a.queue, 1);
+            __syncthreads();
+            const int item = item_sh;
+            if (item >= a.nitems) break;
+            const WorkItem* wip = a.wl + item / a.nsplit;
+            if (a.prob_done != nullptr && a.prob_done[wip->prob]) continue;
+            mvm_f32_item<KERNEL, DP, NSB, RT, ARD>(a, wip, item % a.nsplit, xs, vs);
+        }
+        return;
+    }
+    const WorkItem* wip = (a.wl != nullptr) ? a.wl + blockIdx.x : nullptr;
+    if (wip != nullptr && a.prob_done != nullptr && a.prob_done[wip->prob]) return;
+    mvm_f32_item<KERNEL, DP, NSB, RT, ARD>(a, wip, blockIdx.y, xs, vs);
+}
+
+// blocks of a kernel variant one CU holds (0 if the runtime cannot say)
+template <typename K>
+inline int resident_blocks_per_cu(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+template <int KERNEL, int DP, int NSB, int RT, bool ARD>
+hipError_t launch_f32_variant(const MvmArgs& a, int grid_x, hipStream_t st) {
+    if (a.queue != nullptr) {
+        // persistent grid: the blocks the device holds at once (cached per variant)
+        static int slots = 0;
+        if (slots == 0) {
+            int dev = 0, ncu = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+                slots = std::max(1, resident_blocks_per_cu(mvm_f32_kernel<KERNEL, DP, NSB, RT, ARD>)) * ncu;
+            else
+                slots = 1024;
+            (void)hipGetLastError();
+        }
+        const hipError_t e = launch_fill<int>(a.queue, 1, 0, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, RT, ARD>), dim3(std::min(a.nitems, slots)), dim3(256), 0,
+                           st, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, RT, ARD>), dim3(grid_x, a.nsplit), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int KERNEL, bool ARD, int DP, int NSB>
 hipError_t launch_f32_nsb(const MvmArgs& a, int grid_x, hipStream_t st) {
-    dim3 grid(grid_x, a.nsplit);
     if constexpr (NSB >= 8) {
-        hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 1, ARD>), grid, dim3(256), 0, st, a);
+        return launch_f32_variant<KERNEL, DP, NSB, 1, ARD>(a, grid_x, st);
     } else {
-        if (a.rt == 1)
-            hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 1, ARD>), grid, dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((mvm_f32_kernel<KERNEL, DP, NSB, 2, ARD>), grid, dim3(256), 0, st, a);
+        if (a.rt == 1) return launch_f32_variant<KERNEL, DP, NSB, 1, ARD>(a, grid_x, st);
+        return launch_f32_variant<KERNEL, DP, NSB, 2, ARD>(a, grid_x, st);
     }
-    return hipGetLastError();
 }
 
 template <int KERNEL, bool ARD, int DP>

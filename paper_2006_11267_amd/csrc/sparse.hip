@@ -4,11 +4,31 @@
 // product is this kernel instead of the kernel-matrix product.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ciq_internal.h"
 
 namespace ciq {
 
 namespace {
+
+// Structure check of a caller's CSR operator before any product reads it:
+// row_ptr[0] = 0, row_ptr non-decreasing, row_ptr[n] = nnz and every column
+// index in [0, n). Reads only row_ptr[0..n] and col[0..nnz); sets *bad on a
+// violation.
+__global__ void csr_check_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col, int n, int nnz,
+                                 int* bad) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long i = t; i <= n; i += stride) {
+        const int r = row_ptr[i];
+        if ((i == 0 && r != 0) || (i == n && r != nnz) || (i < n && row_ptr[i + 1] < r)) atomicOr(bad, 1);
+    }
+    for (long long k = t; k < nnz; k += stride) {
+        const int c = col[k];
+        if (c < 0 || c >= n) atomicOr(bad, 1);
+    }
+}
 
 // y[i][c] = sum_k val[k] x[col[k]][c] over row i's entries (s > 1). Block: TS columns
 // x RL rows (TS = the power of two >= s, at most 64); each thread one (row,
@@ -45,6 +65,13 @@ __global__ __launch_bounds__(256) void spmv1_kernel(SparseOp a, const double* __
 }
 
 }  // namespace
+
+hipError_t launch_csr_check(const int* row_ptr, const int* col, int n, int nnz, int* bad, hipStream_t st) {
+    const long long work = std::max((long long)n + 1, (long long)nnz);
+    const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
+    hipLaunchKernelGGL(csr_check_kernel, dim3(blocks), dim3(256), 0, st, row_ptr, col, n, nnz, bad);
+    return hipGetLastError();
+}
 
 hipError_t launch_spmv(const SparseOp& a, const double* x, int ldx, int s, double* y, int ldy, const int* done,
                        hipStream_t st) {

@@ -313,8 +313,12 @@ def ciq_pivoted_cholesky(problem: Problem, rank: int):
 
 def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tensor], q: int = 12,
                             max_iter: int = 1000, tol: float = 1e-4, bounds=None, lanczos_steps: int = 0,
-                            seed: int = 0, check_every: int = 0, profile: bool = False, graph: bool = False):
-    """[K_p^{-1/2} B_p] for independent problems in one run -> (outs, infos)."""
+                            seed: int = 0, check_every: int = 0, profile: bool = False, graph: bool = True,
+                            kernel_cache: str = "auto"):
+    """[K_p^{-1/2} B_p] for independent problems in one run -> (outs, infos).
+    The iteration's kernels (one persistent product over all problems' row
+    blocks, inner products, scalar stage, update) are replayed from a HIP
+    graph unless graph=False or profile=True."""
     lib = L.load()
     P = len(problems)
     s = bs[0].shape[1]
@@ -329,7 +333,8 @@ def ciq_invsqrt_mvm_batched(problems: Sequence[Problem], bs: Sequence[torch.Tens
     bp = (ctypes.c_void_p * P)(*[b.data_ptr() for b in bcont])
     op = (ctypes.c_void_p * P)(*[o.data_ptr() for o in outs])
     infos = (L.ciq_info * P)()
-    o = _opts(L.CIQ_F32, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, graph=graph)
+    o = _opts(L.CIQ_F32, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, graph=graph,
+              kernel_cache=kernel_cache)
     L.check(lib.ciq_invsqrt_mvm_batched(P, parr, ctypes.byref(o), bp, s, op, infos, _stream()),
             "ciq_invsqrt_mvm_batched")
     del keeps

@@ -108,9 +108,28 @@ def test_setup_rejects(lib):
     assert lib.ciq_setup(1.0, 2.0, 3, None, None) == L.CIQ_EINVAL
 
 
+_KEEP = []
+
+
+def _dev_ptr(nbytes=4096):
+    """A small valid device buffer when a GPU is present, so that a validation
+    regression shows as a wrong return code rather than device work on a bad
+    address; without a GPU any non-null address serves (no device work may
+    start, and none can)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            t = torch.zeros(max(nbytes // 8, 1), dtype=torch.float64, device="cuda")
+            _KEEP.append(t)
+            return ctypes.c_void_p(t.data_ptr())
+    except ImportError:
+        pass
+    return ctypes.c_void_p(512)
+
+
 def _bad_problem(**kw):
     ls = (ctypes.c_double * 1)(0.3)
-    fields = dict(n=10, d=3, x=ctypes.c_void_p(256), kernel=0, n_lengthscale=1,
+    fields = dict(n=10, d=3, x=_dev_ptr(), kernel=0, n_lengthscale=1,
                   lengthscale=ctypes.cast(ls, ctypes.POINTER(ctypes.c_double)), outputscale=1.0, noise=0.1)
     fields.update(kw)
     return L.ciq_problem(**fields), ls
@@ -122,7 +141,7 @@ def test_invalid_problem_rejected_before_device_work(lib, bad):
     p, keep = _bad_problem(**bad)
     o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4)
     info = L.ciq_info()
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     for fn in (lib.ciq_invsqrt_mvm, lib.ciq_sqrt_mvm):
         assert fn(ctypes.byref(p), ctypes.byref(o), fake, 2, 2, fake, 2, None, ctypes.byref(info), None) \
             == L.CIQ_EINVAL
@@ -142,7 +161,7 @@ def test_invalid_options_rejected(lib, bad):
     for k, v in bad.items():
         setattr(o, k, v)
     info = L.ciq_info()
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     assert lib.ciq_invsqrt_mvm(ctypes.byref(p), ctypes.byref(o), fake, 2, 2, fake, 2, None, ctypes.byref(info),
                                None) == L.CIQ_EINVAL
     del keep
@@ -152,7 +171,7 @@ def test_invalid_sizes_rejected(lib):
     p, keep = _bad_problem()
     o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4)
     info = L.ciq_info()
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     for s, ldb, ldo in [(0, 1, 1), (4, 3, 4), (4, 4, 3)]:
         assert lib.ciq_invsqrt_mvm(ctypes.byref(p), ctypes.byref(o), fake, s, ldb, fake, ldo, None,
                                    ctypes.byref(info), None) == L.CIQ_EINVAL
@@ -161,7 +180,7 @@ def test_invalid_sizes_rejected(lib):
     assert lib.ciq_invsqrt_mvm(ctypes.byref(p), ctypes.byref(o), fake, 2, 2, fake, 2, None, None, None) \
         == L.CIQ_EINVAL
     probs = (L.ciq_problem * 1)(p)
-    bp = (ctypes.c_void_p * 1)(512)
+    bp = (ctypes.c_void_p * 1)(_dev_ptr().value)
     infos = (L.ciq_info * 1)()
     assert lib.ciq_invsqrt_mvm_batched(0, probs, ctypes.byref(o), bp, 2, bp, infos, None) == L.CIQ_EINVAL
     del keep
@@ -171,7 +190,7 @@ def test_preconditioner_arguments_rejected(lib):
     """Preconditioning needs sigma^2 > 0; the batched call and the backward do
     not take it; the factor entry validates rank and pointers. All checked
     before any device work."""
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     info = L.ciq_info()
     p0, keep0 = _bad_problem(noise=0.0)
     o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4, precond_rank=4)
@@ -179,7 +198,7 @@ def test_preconditioner_arguments_rejected(lib):
                             None) == L.CIQ_EINVAL
     p, keep = _bad_problem()
     probs = (L.ciq_problem * 1)(p)
-    bp = (ctypes.c_void_p * 1)(512)
+    bp = (ctypes.c_void_p * 1)(_dev_ptr().value)
     infos = (L.ciq_info * 1)()
     assert lib.ciq_invsqrt_mvm_batched(1, probs, ctypes.byref(o), bp, 2, bp, infos, None) == L.CIQ_ENOTSUP
     t = (ctypes.c_double * 8)(*([1.0] * 8))
@@ -200,7 +219,7 @@ def test_posterior_arguments_rejected(lib):
     p, keep = _bad_problem()
     o = L.ciq_opts(dtype=L.CIQ_F32, q=8, max_iter=10, tol=1e-4)
     info = L.ciq_info()
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     args = dict(x=fake, n=5, noise=1e-2, mode=L.CIQ_SQRT)
     for bad in [dict(x=None), dict(n=0), dict(n=4097), dict(noise=-1.0), dict(noise=float("nan")), dict(mode=7)]:
         a = {**args, **bad}
@@ -213,7 +232,7 @@ def test_posterior_arguments_rejected(lib):
 
 
 def test_csr_arguments_rejected(lib):
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     info = L.ciq_info()
     o = L.ciq_opts(dtype=L.CIQ_F64, q=8, max_iter=10, tol=1e-4)
     good = dict(n=10, nnz=30, row_ptr=fake, col_idx=fake, val=fake)
@@ -233,7 +252,7 @@ def test_csr_arguments_rejected(lib):
 
 def test_svgp_arguments_rejected(lib):
     p, keep = _bad_problem()
-    fake = ctypes.c_void_p(512)
+    fake = _dev_ptr()
     info = L.ciq_info()
     o = L.ciq_opts(dtype=L.CIQ_F64, q=8, max_iter=10, tol=1e-4)
     good = dict(x=fake, nb=4, theta=fake, Theta=fake, it=10, tol=1e-8, mean=fake, var=fake)

@@ -227,6 +227,44 @@ def test_fp32_matches_fp64_oracle(kind, n, s, d, cache):
         assert err < 1e-4, (mode, err, info["iters"])
 
 
+@pytest.mark.parametrize("s", [16, 32])
+def test_fp32_resident_inverse_root_has_no_accumulation_error(s):
+    """The FP32 resident inverse root at <= 32 columns contracts the FP32
+    entries on the FP64 MFMA: its result is the solve on the FP32-rounded
+    matrix itself. Held to the oracle's msMINRES-CIQ on that matrix (the
+    FP64 kernel entries rounded to FP32 once, the noise added in FP64) at
+    5e-6, on a problem where FP32 sums cost several 1e-5 (d = 3, lengthscale
+    0.25, noise 1e-2: strongly correlated rows). Against the unrounded
+    matrix the error is then the rounding's own, below 1e-4. Bounds: the
+    noise and the largest absolute row sum (Gershgorin), on both sides."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(77 + s)
+    n, d, noise = 4000, 3, 1e-2
+    x = rng.random((n, d)).astype(np.float32)
+    b = rng.standard_normal((n, s)).astype(np.float32)
+    Kk = okern.kernel_matrix("rbf", x.astype(np.float64), [0.25], 1.0, 0.0)
+    K = Kk + noise * np.eye(n)
+    K32 = Kk.astype(np.float32).astype(np.float64) + noise * np.eye(n)
+    del Kk
+    bounds = (noise, float(np.abs(K).sum(axis=1).max()))
+    announce(f"ciq f32 resident inverse root vs oracle on the rounded matrix n={n} s={s}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), "rbf", [0.25], 1.0, noise)
+    out, info, _ = ciq.ciq_invsqrt_mvm(prob, torch.from_numpy(b).cuda(), q=12, max_iter=3000, tol=1e-9,
+                                       bounds=bounds, kernel_cache="on")
+    assert info["kernel_cached"] and info["converged"]
+    out = out.cpu().numpy()
+    b64 = b.astype(np.float64)
+    ref32, _ = ociq.ciq(lambda v: K32 @ v, b64, bounds[0], bounds[1], 12, 3000, 1e-11)
+    ref, _ = ociq.ciq(lambda v: K @ v, b64, bounds[0], bounds[1], 12, 3000, 1e-11)
+    own = colwise_rel(out, ref32).max()
+    full = colwise_rel(out, ref).max()
+    print(f"s={s}: vs rounded-matrix oracle {own:.2e}, vs exact-matrix oracle {full:.2e} "
+          f"({info['iters']} iterations)", flush=True)
+    assert own < 5e-6, own
+    assert full < 1e-4, full
+
+
 @pytest.mark.parametrize("prec,cache,bar", [("bf16x3", "off", 5e-3), ("f16x3", "off", 5e-4), ("f16x3", "on", 1e-4)])
 def test_split_forms_against_exact(prec, cache, bar):
     """The split-operand BF16 / FP16 products inside a full CIQ solve: the

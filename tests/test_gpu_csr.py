@@ -74,3 +74,37 @@ def test_csr_converged_parity(n_img, s):
         print(f"{mode}: rel err {err:.2e}, iters {info['iters']} (oracle {oinfo.iters}), bounds "
               f"{info['lambda_min']:.3g} {info['lambda_max']:.3g}", flush=True)
         assert err < 1e-8
+
+
+@pytest.mark.parametrize("defect", ["col_high", "col_negative", "row_ptr_decreasing", "row_ptr_end", "row_ptr_start"])
+def test_malformed_csr_rejected(defect):
+    """A malformed CSR structure is CIQ_EINVAL from the device structure check
+    before any product reads it (the arrays keep their sizes, so the check
+    itself reads only in-bounds entries)."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    import paper_2006_11267_amd._lib as L
+    A = gibbs.gibbs_precision(12, 1.0, 0.01)
+    indptr, indices = A.indptr.astype(np.int32).copy(), A.indices.astype(np.int32).copy()
+    n = A.shape[0]
+    if defect == "col_high":
+        indices[5] = n
+    elif defect == "col_negative":
+        indices[-1] = -3
+    elif defect == "row_ptr_decreasing":
+        indptr[7] = indptr[6] - 1
+    elif defect == "row_ptr_end":
+        indptr[-1] -= 1
+    else:
+        indptr[0] = 1
+    announce(f"csr malformed {defect}")
+    b = torch.from_numpy(_rhs(n, 2, 4)).cuda()
+    csr = (torch.from_numpy(indptr).cuda(), torch.from_numpy(indices).cuda(), torch.from_numpy(A.data).cuda())
+    with pytest.raises(L.CIQError) as ei:
+        ciq.ciq_csr_mvm(*csr, b, q=6, max_iter=5, tol=0.0, bounds=(0.01, 10.0))
+    assert ei.value.status == L.CIQ_EINVAL
+    # the well-formed operator passes the check
+    good = (torch.from_numpy(A.indptr.astype(np.int32)).cuda(), torch.from_numpy(A.indices.astype(np.int32)).cuda(),
+            torch.from_numpy(A.data).cuda())
+    res, info = ciq.ciq_csr_mvm(*good, b, q=6, max_iter=5, tol=0.0, bounds=(0.01, 10.0))
+    assert info["iters"] == 5
