@@ -296,6 +296,20 @@ hipError_t launch_lr_dotsum(const double* dotp, int nblk, int S, double* out, co
 // on the differences), out row-major with leading dimension ldo >= nb.
 hipError_t launch_xkernel(const double* xa, int na, const double* xb, int nb, int dp, int kernel, int ard,
                           const double* scale, double o2, double* out, int ldo, hipStream_t st);
+// ---- observation-block factors of the posterior (chol.hip) ------------------
+// A (npad x npad, row-major, zero-filled outside the leading n x n): A[i][i]
+// += shift for i < n, identity on the padded diagonal.
+hipError_t launch_chol_prep(double* A, int n, int npad, double shift, hipStream_t st);
+// In-place lower Cholesky factor of A (npad a multiple of 64; the strict
+// upper part of each diagonal block is zeroed, the rest of the upper
+// triangle is left unspecified); dinv[k] (64 x 64 each) = inverse of
+// diagonal block k. *status |= 1 if a pivot is not positive (the caller
+// zeroes it).
+hipError_t launch_chol_blocked(double* A, int npad, double* dinv, int* status, hipStream_t st);
+// W <- W L^{-T} in place for W rows x npad (ld npad), L and dinv from
+// launch_chol_blocked.
+hipError_t launch_trsm_right_lt(double* W, int rows, int npad, const double* L, const double* dinv, hipStream_t st);
+
 // ---- sparse symmetric operator (sparse.hip) ----------------------------------
 struct SparseOp {
     int n;                   // rows = columns

@@ -415,7 +415,8 @@ int pc_build(const ciq_problem& p, const double* xh, int dp, int kernel, int ard
 
 // ---- posterior covariance at a candidate set (Sec. 5.2) ---------------------
 // Sigma = Kss + jitter I - W W^T with W = Ksx L^{-T}, L L^T = Kxx + sigma_obs^2 I
-// (Cholesky of the small observation block on the host). Every product with
+// (blocked Cholesky of the observation block and the triangular solve for W
+// on the device, chol.hip). Every product with
 // Sigma is the candidate kernel product plus the low-rank correction
 // -W (W^T v), accumulated into the product's first partial.
 struct PostSpec {
@@ -426,67 +427,38 @@ struct PostSpec {
 
 struct Posterior {
     int n = 0;              // observations
-    double* W = nullptr;    // T x n
+    int ldw = 0;            // leading dimension of W: n rounded up to 64
+    double* W = nullptr;    // T x ldw (columns n.. zero)
     double* fneg = nullptr; // [n] of -1
     double* part = nullptr; // low-rank partials
-    double* T = nullptr;    // n x max(s, n)
+    double* T = nullptr;    // n x s
     DevAlloc mem;
 };
 
-// In-place lower Cholesky factor of a row-major SPD matrix (row-oriented:
-// every inner product runs over two contiguous rows). False if not SPD.
-bool chol_lower(int n, std::vector<double>& a) {
-    for (int i = 0; i < n; ++i) {
-        double* ai = &a[(size_t)i * n];
-        for (int j = 0; j <= i; ++j) {
-            const double* aj = &a[(size_t)j * n];
-            double t = ai[j];
-            for (int k = 0; k < j; ++k) t -= ai[k] * aj[k];
-            if (i == j) {
-                if (!(t > 0.0) || !std::isfinite(t)) return false;
-                ai[i] = std::sqrt(t);
-            } else {
-                ai[j] = t / aj[j];
-            }
-        }
-    }
-    return true;
-}
-
-// mt[j][i] = (L^{-1})[i][j]: row j of mt is the forward-substitution solve of
-// L x = e_j (zero above j).
-void tri_inv_transposed(int n, const std::vector<double>& L, std::vector<double>& mt) {
-    mt.assign((size_t)n * n, 0.0);
-    for (int j = 0; j < n; ++j) {
-        double* x = &mt[(size_t)j * n];
-        x[j] = 1.0 / L[(size_t)j * n + j];
-        for (int i = j + 1; i < n; ++i) {
-            const double* li = &L[(size_t)i * n];
-            double t = 0.0;
-            for (int k = j; k < i; ++k) t += li[k] * x[k];
-            x[i] = -t / li[i];
-        }
-    }
-}
-
-// Sigma's correction for candidates with FP64 points xh (T x dp).
+// Sigma's correction for candidates with FP64 points xh (T x dp): Kxx and
+// Ksx into blocks padded to npad = 64 ceil(n / 64) columns, the factor and
+// W = Ksx L^{-T} (in place of Ksx) on the device. Synchronous.
 int post_build(const ciq_problem& cand, int dtype, const double* xh, int dp, int kernel, int ard,
                const double* scale, const PostSpec& ps, int s_cap, Posterior& po, hipStream_t st) {
     const int T = cand.n, n = ps.n_obs;
+    const int npad = (n + 63) / 64 * 64;
     po.n = n;
+    po.ldw = npad;
     size_t part_n = 0;
     for (int w : {s_cap, 1}) part_n = std::max(part_n, (size_t)lr_part_chunks(T, n, w) * n * w);
     size_t off = 0;
-    double *xo = nullptr, *kxx = nullptr, *ksx = nullptr;
+    double *xo = nullptr, *kxx = nullptr, *dinv = nullptr;
+    int* status = nullptr;
     auto layout = [&](char* base) {
         off = 0;
-        po.W = carve<double>(base, off, (size_t)T * n);
-        ksx = carve<double>(base, off, (size_t)T * n);
+        po.W = carve<double>(base, off, (size_t)T * npad);
         xo = carve<double>(base, off, (size_t)n * dp);
-        kxx = carve<double>(base, off, (size_t)n * n);
+        kxx = carve<double>(base, off, (size_t)npad * npad);
+        dinv = carve<double>(base, off, (size_t)npad * 64);
+        status = reinterpret_cast<int*>(carve<double>(base, off, 1));
         po.fneg = carve<double>(base, off, n);
         po.part = carve<double>(base, off, part_n);
-        po.T = carve<double>(base, off, (size_t)n * std::max(s_cap, n));
+        po.T = carve<double>(base, off, (size_t)n * s_cap);
     };
     layout(nullptr);
     if (hipMalloc(&po.mem.p, off) != hipSuccess) {
@@ -501,20 +473,19 @@ int post_build(const ciq_problem& cand, int dtype, const double* xh, int dp, int
         HIPCHK(launch_prep<double>(static_cast<const double*>(ps.x_obs), n, cand.d, dp, ones, xo, st));
     else
         HIPCHK(launch_prep<float>(static_cast<const float*>(ps.x_obs), n, cand.d, dp, ones, xo, st));
-    HIPCHK(launch_xkernel(xo, n, xo, n, dp, kernel, ard, scale, cand.outputscale, kxx, n, st));
-    HIPCHK(launch_xkernel(xh, T, xo, n, dp, kernel, ard, scale, cand.outputscale, ksx, n, st));
+    HIPCHK(launch_fill<double>(kxx, (size_t)npad * npad, 0.0, st));
+    HIPCHK(launch_xkernel(xo, n, xo, n, dp, kernel, ard, scale, cand.outputscale, kxx, npad, st));
+    HIPCHK(launch_chol_prep(kxx, n, npad, ps.obs_noise, st));
+    if (npad > n) HIPCHK(launch_fill<double>(po.W, (size_t)T * npad, 0.0, st));
+    HIPCHK(launch_xkernel(xh, T, xo, n, dp, kernel, ard, scale, cand.outputscale, po.W, npad, st));
     HIPCHK(launch_fill<double>(po.fneg, n, -1.0, st));
-    std::vector<double> K((size_t)n * n), mt;
-    HIPCHK(hipMemcpyAsync(K.data(), kxx, K.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_fill<int>(status, 1, 0, st));
+    HIPCHK(launch_chol_blocked(kxx, npad, dinv, status, st));
+    HIPCHK(launch_trsm_right_lt(po.W, T, npad, kxx, dinv, st));
+    int h_status = 0;
+    HIPCHK(hipMemcpyAsync(&h_status, status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    for (int i = 0; i < n; ++i) K[(size_t)i * n + i] += ps.obs_noise;
-    if (!chol_lower(n, K)) return CIQ_ENUMERIC;
-    tri_inv_transposed(n, K, mt);
-    HIPCHK(hipMemcpyAsync(po.T, mt.data(), mt.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    // W = Ksx L^{-T} (FP64 MFMA)
-    HIPCHK(launch_lr_apply(0.0, nullptr, 0, ksx, n, po.T, n, T, n, n, po.W, n, nullptr, nullptr, nullptr, st));
-    HIPCHK(hipStreamSynchronize(st));   // mt is a pageable host vector
-    return CIQ_OK;
+    return h_status ? CIQ_ENUMERIC : CIQ_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -826,9 +797,9 @@ struct Run {
     int post_correct(const double* v, const int* done, hipStream_t st) {
         if (!post) return CIQ_OK;
         const int nch = lr_part_chunks(rows_total, post->n, s);
-        HIPCHK(launch_lr_part(post->W, post->n, v, s, rows_total, post->n, s, nch, post->part, done, st));
+        HIPCHK(launch_lr_part(post->W, post->ldw, v, s, rows_total, post->n, s, nch, post->part, done, st));
         HIPCHK(launch_lr_reduce(post->part, nch, post->n, s, post->fneg, post->T, s, done, st));
-        HIPCHK(launch_lr_apply(0.0, nullptr, 0, post->W, post->n, post->T, s, rows_total, post->n, s, ypart, s,
+        HIPCHK(launch_lr_apply(0.0, nullptr, 0, post->W, post->ldw, post->T, s, rows_total, post->n, s, ypart, s,
                                nullptr, nullptr, done, st, 1));
         return CIQ_OK;
     }

@@ -55,6 +55,32 @@ def test_posterior_small_j_parity_fp64(mode, J, cache):
     assert gap < bar
 
 
+@pytest.mark.parametrize("n_obs", [1, 63, 64, 65, 130, 257])
+def test_posterior_observation_counts(n_obs):
+    """The device factors of the observation block (64-column panels, the
+    block padded with the identity) at counts below, at, just above and
+    across panel boundaries: converged FP64 K^{1/2}-root against the oracle's
+    CIQ on the dense Sigma (the textbook posterior covariance) with the same
+    bounds, to 1e-8."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    t, d, s = 700, 3, 5
+    kind, ls, o2, jit, s2 = "rbf", [0.3], 1.1, 1e-2, 1e-3
+    xs, xo, b = _inputs(t, n_obs, d, s, 100 + n_obs)
+    S = opost.posterior_covariance(kind, xs, xo, ls, o2, jit, s2)
+    lam = np.linalg.eigvalsh(S)
+    bounds = (lam[0], lam[-1])
+    announce(f"posterior observation count n_obs={n_obs}")
+    prob = ciq.Problem(torch.from_numpy(xs).cuda(), kind, ls, o2, jit)
+    out, info = ciq.ciq_posterior_mvm(prob, torch.from_numpy(xo).cuda(), s2, torch.from_numpy(b).cuda(),
+                                      mode="sqrt", q=12, max_iter=2000, tol=1e-11, bounds=bounds)
+    assert info["converged"] and info["setup_ms"] > 0.0
+    ref, _ = oc.ciq(lambda v: S @ v, b, bounds[0], bounds[1], 12, 2000, 1e-12, "sqrt")
+    err = colwise_rel(out.cpu().numpy(), ref).max()
+    print(f"n_obs={n_obs}: rel err {err:.2e}, iters {info['iters']}, set-up {info['setup_ms']:.1f} ms", flush=True)
+    assert err < 1e-8
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_posterior_converged_parity(prec):
     """Converged (library bounds), FP64 to 1e-7, FP32 products to 2e-4, both
