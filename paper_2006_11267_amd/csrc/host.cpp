@@ -833,6 +833,18 @@ struct Run {
     // replays are the same work as the eager loop.
     int iterate(hipStream_t st, int check_every, IterState* pinned, int* mvm_count,
                 hipEvent_t* ev_pool, int n_ev, double* mvm_ms, int* mvm_timed, bool use_graph = false) {
+        // $CIQ_PROGRESS set: a line on stderr with the iteration count at the
+        // host's convergence checks, at most one per 10 s (long solves)
+        static const bool progress = std::getenv("CIQ_PROGRESS") != nullptr;
+        auto last = std::chrono::steady_clock::now();
+        auto report = [&]() {
+            if (!progress) return;
+            const auto now = std::chrono::steady_clock::now();
+            if (std::chrono::duration<double>(now - last).count() < 10.0) return;
+            last = now;
+            std::fprintf(stderr, "[ciq] iteration %d of at most %d\n", pinned->iter, max_iter);
+            std::fflush(stderr);
+        };
         // the state is reused scratch: clear `done` before the first kernel that reads it
         HIPCHK(launch_fill<int>(reinterpret_cast<int*>(d.st), sizeof(IterState) / sizeof(int), 0, st));
         if (vt16)      // rows past n and columns past s of the split operand stay zero
@@ -886,6 +898,7 @@ struct Run {
                     HIPCHK(hipStreamSynchronize(st));
                     if (pinned->numeric) return CIQ_ENUMERIC;
                     if (pinned->done) break;
+                    report();
                 }
             }
         } else {
@@ -918,6 +931,7 @@ struct Run {
                     }
                     if (pinned->numeric) return CIQ_ENUMERIC;
                     if (pinned->done) break;
+                    report();
                 }
                 ++j;
             }

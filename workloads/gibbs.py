@@ -71,7 +71,7 @@ def decimation_matrix(n: int) -> sp.csr_matrix:
     return sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(4 * m * m, n * n))
 
 
-def gibbs_precision(n: int = 160, g_obs: float = 1.0, g_prior: float = 0.05) -> sp.csr_matrix:
+def gibbs_precision(n: int = 160, g_obs: float = 1.0, g_prior: float = 0.01) -> sp.csr_matrix:
     """Lam (n^2 x n^2, CSR, FP64, sorted column indices, exactly symmetric)."""
     B = correlation_matrix(n, gaussian_filter())
     A = decimation_matrix(n) @ B
