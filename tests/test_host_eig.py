@@ -44,7 +44,7 @@ def driver(tmp_path_factory):
     d = tmp_path_factory.mktemp("eig")
     (d / "drv.cpp").write_text(DRIVER)
     exe = d / "drv"
-    r = subprocess.run(["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+    r = subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
                         "-I" + os.path.join(ROOT, "include"), str(d / "drv.cpp"), SRC, "-o", str(exe)],
                        capture_output=True, text=True)
     if r.returncode != 0:
@@ -64,7 +64,7 @@ def _eig(driver, method, A):
 def _cases():
     rng = np.random.default_rng(0)
     out = []
-    for n in (1, 2, 3, 7, 40, 150):
+    for n in (1, 2, 3, 7, 40, 150, 400):      # from n = 128 on, the tridiagonal solver runs on a thread team
         X = rng.standard_normal((3 * n, n)) * np.exp(-0.05 * np.arange(n))
         out.append((f"gram{n}", X.T @ X))
     X = rng.standard_normal((80, 25))
