@@ -85,6 +85,9 @@ extern "C" {
 #define CIQ_INVSQRT 0
 #define CIQ_SQRT    1
 
+#define CIQ_BASIS_AUTO 0
+#define CIQ_BASIS_OFF  1
+
 #define CIQ_CACHE_AUTO 0   /* keep K resident when it fits (see ciq_opts.kernel_cache) */
 #define CIQ_CACHE_OFF  1   /* evaluate kernel entries in every product                */
 #define CIQ_CACHE_ON   2   /* always keep K resident (CIQ_ENOMEM if it does not fit)  */
@@ -167,7 +170,17 @@ typedef struct ciq_opts {
                                   max_rel_residual refer to the preconditioned
                                   system. 0: plain CIQ. ciq_backward and the batched
                                   call return CIQ_ENOTSUP for R > 0.             */
-    int32_t reserved[2];
+    int32_t krylov_basis;      /* CIQ_BASIS_AUTO: when the run has neither a
+                                  preconditioner nor kept per-shift solves and
+                                  (max_iter + 1) Lanczos vectors fit in device
+                                  memory, keep them all resident (allocated and
+                                  freed inside the call) and form the solution
+                                  once after the run from the logged direction
+                                  coefficients, instead of moving Q direction
+                                  vectors every iteration (the same result up to
+                                  rounding). CIQ_BASIS_OFF: the direction
+                                  recurrence.                                    */
+    int32_t reserved;
 } ciq_opts;
 
 /* Per-call report (host). Valid when the call returned CIQ_OK. */
@@ -191,6 +204,7 @@ typedef struct ciq_info {
     double setup_ms;           /* host wall time (ms) of the preconditioner's or the
                                   posterior's factors, built before the Krylov runs
                                   (0 when the call has neither)                     */
+    int32_t krylov_basis;      /* 1 if the run kept its Lanczos basis resident       */
 } ciq_info;
 
 /* Library version (major*10000 + minor*100 + patch). */

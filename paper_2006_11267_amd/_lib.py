@@ -66,7 +66,8 @@ class ciq_opts(ctypes.Structure):
         ("cache_budget_mib", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("precond_rank", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("krylov_basis", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -87,6 +88,7 @@ class ciq_info(ctypes.Structure):
         ("precond_rank", ctypes.c_int32),
         ("precond_trace", ctypes.c_double),
         ("setup_ms", ctypes.c_double),
+        ("krylov_basis", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -107,6 +109,7 @@ class ciq_info(ctypes.Structure):
             "precond_rank": self.precond_rank,
             "precond_trace": self.precond_trace,
             "setup_ms": self.setup_ms,
+            "krylov_basis": bool(self.krylov_basis),
         }
 
 

@@ -68,6 +68,14 @@ struct Dev {
     int* frozen;
     ShiftCoef* coef;
     IterState* st;
+    // resident Krylov basis (nullptr: the direction recurrence): the scalar
+    // stage logs each iteration's direction coefficients, the update stores
+    // q_{j+1} in slot j instead of moving the per-shift directions, and the
+    // combination sum_j c_j q_j is formed once after the run
+    double* clog;           // [max_iter][Q * ncol][4]: delta, eps, ginv, tauw
+    double* basis;          // [basis_slots][rows_total * s]: slot k holds q_{k+1}
+    long long bstride;      // elements per slot (rows_total * s)
+    int basis_slots;
 };
 
 // Tiled split-FP16 copy of an FP64 block vector (rows x s, point-major), the
@@ -225,6 +233,13 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
 
 // pvec (nullable): preconditioned start, pvec <- pvec / beta_1 too and q32
 // copies pvec instead of q.
+// After a run with the resident basis: acc = sum_j c_j q_j per column, the
+// coefficients c_j by back-substitution of the logged direction recurrence
+// of every (shift, column). cq: [iters][Q * ncol], c: [iters][ncol] doubles
+// of scratch; iters = the run's iteration count.
+hipError_t launch_basis_combine(const Dev& d, int iters, double* cq, double* c, double* acc, int max_n,
+                                hipStream_t st);
+
 template <typename T>
 hipError_t launch_init_vectors(const Dev& d, T* q, T* qprev, T* acc, float* q32, int rows,
                                hipStream_t st, T* pvec = nullptr, Op16 op = Op16{nullptr, 0, 1.0f});

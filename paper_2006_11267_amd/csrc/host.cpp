@@ -859,13 +859,16 @@ struct Run {
             HIPCHK(launch_colsum(d, 1, st));
         }
         HIPCHK(launch_scalar_init(d, st));
-        if (Q > 0) {
+        if (Q > 0 && d.basis == nullptr) {   // the direction recurrence's m_{-1}, m_0
             HIPCHK(launch_fill<double>(mbuf[0], (size_t)rows_total * s * Q, 0.0, st));
             HIPCHK(launch_fill<double>(mbuf[1], (size_t)rows_total * s * Q, 0.0, st));
         }
         if (solves) HIPCHK(launch_fill<double>(solves, (size_t)rows_total * s * Q, 0.0, st));
         HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st,
                                            precond ? pbuf[0] : nullptr, op16()));
+        if (d.basis)   // slot 0: q_1
+            HIPCHK(hipMemcpyAsync(d.basis, qbuf[0], (size_t)rows_total * s * sizeof(double), hipMemcpyDeviceToDevice,
+                                  st));
         if (use_graph && ev_pool == nullptr) {
             hipStream_t cs = nullptr;
             hipGraph_t graph = nullptr;
@@ -1349,9 +1352,41 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         STCHK(tune_rt(main, main.qbuf[0], st));
     }
 
+    // ---- resident Krylov basis (when it fits; allocated for this call) -----
+    DevAlloc basis_mem;
+    double *basis_cq = nullptr, *basis_c = nullptr;
+    bool use_basis = false;
+    if (o->krylov_basis == CIQ_BASIS_AUTO && !precond && solves_out == nullptr && main.Q > 0) {
+        const size_t slots = (size_t)main.max_iter + 1;
+        const size_t vec = (size_t)main.rows_total * s;
+        const size_t qn = (size_t)main.Q * main.d.ncol;
+        const size_t iters_cap = (size_t)main.max_iter;
+        const size_t bytes =
+            (slots * vec + iters_cap * qn * 4 + iters_cap * qn + iters_cap * main.d.ncol) * sizeof(double) + 4 * 256;
+        size_t free_b = 0, total_b = 0;
+        // leave a tenth of the free memory and 4 GiB for everything else
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes + (size_t(4) << 30) <= free_b / 10 * 9 &&
+            hipMalloc(&basis_mem.p, bytes) == hipSuccess) {
+            size_t off = 0;
+            char* base = static_cast<char*>(basis_mem.p);
+            main.d.basis = carve<double>(base, off, slots * vec);
+            main.d.clog = carve<double>(base, off, iters_cap * qn * 4);
+            basis_cq = carve<double>(base, off, iters_cap * qn);
+            basis_c = carve<double>(base, off, iters_cap * main.d.ncol);
+            main.d.bstride = (long long)vec;
+            main.d.basis_slots = (int)slots;
+            use_basis = true;
+        } else {
+            (void)hipGetLastError();
+            basis_mem.p = nullptr;
+        }
+    }
+
     STCHK(main.iterate(st, check_every, pinned, &mvm_count, profile ? evs.data() : nullptr,
                        profile ? check_every : 0, &mvm_ms, &mvm_timed, o->graph == 1));
     const int iters = pinned->iter;
+    if (use_basis && iters > 0)
+        HIPCHK(launch_basis_combine(main.d, iters, basis_cq, basis_c, main.acc, main.max_n, st));
 
     // ---- combine -----------------------------------------------------------
     if (mode == CIQ_SQRT) {
@@ -1431,6 +1466,7 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         in.precond_rank = precond ? pc.rank : 0;
         in.precond_trace = precond ? pc.trace : 0.0;
         in.setup_ms = setup_ms;
+        in.krylov_basis = use_basis ? 1 : 0;
     }
     return CIQ_OK;
 }
@@ -1443,6 +1479,7 @@ int check_solve_args(const ciq_problem* p, const ciq_opts* o, const void* b, int
     if (o->q < 1 || o->q > CIQ_MAX_Q || o->max_iter < 1) return CIQ_EINVAL;
     if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return CIQ_EINVAL;
     if (o->lanczos_steps < 0 || o->check_every < 0) return CIQ_EINVAL;
+    if (o->krylov_basis != CIQ_BASIS_AUTO && o->krylov_basis != CIQ_BASIS_OFF) return CIQ_EINVAL;
     if (o->precond_rank < 0 || o->precond_rank > CIQ_MAX_RANK) return CIQ_EINVAL;
     if (o->precond_rank > 0 && !(p->noise > 0.0)) return CIQ_EINVAL;   // P = Lbar Lbar^T + sigma^2 I
     return CIQ_OK;

@@ -487,6 +487,13 @@ __device__ void scalar_stage(const Dev& d, int tid, int nt, int* active_cnt, int
             if (rr <= d.tol) d.frozen[idx] = 1;
         }
         d.coef[idx] = cf;
+        if (d.clog != nullptr) {
+            double* lg = d.clog + ((long long)iter * Q * ncol + idx) * 4;
+            lg[0] = cf.delta;
+            lg[1] = cf.eps;
+            lg[2] = cf.ginv;
+            lg[3] = cf.tauw;
+        }
     }
     __syncthreads();
 
@@ -568,7 +575,11 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
     extern __shared__ char smem[];
     if (!d.st->live) return;
     const int RL = 256 / TS;
-    const int Q = d.Q, s = d.s, ncol = d.ncol;
+    const int s = d.s, ncol = d.ncol;
+    // resident basis: no per-shift directions move; q_{j+1} goes to slot j
+    const bool basis = d.basis != nullptr;
+    const int Q = basis ? 0 : d.Q;
+    const int slot = d.st->iter;
     T* sdelta = reinterpret_cast<T*>(smem);
     T* seps = sdelta + Q * TS;
     T* sginv = seps + Q * TS;
@@ -615,7 +626,7 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
             a += stauw[e] * m;
             if (solves) solves[(row * Q + q) * s + c] += stau[e] * m;
         }
-        acc[idx] += a;
+        if (!basis) acc[idx] += a;
         if (flag == 2) {
             if (pnext) {                        // preconditioned: y is w = z_{j+1} beta_{j+1}
                 qprev[idx] = y[idx] * ib;
@@ -631,6 +642,7 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
             const T v = vT - al * qj;
             const T qn = v * ib;
             qprev[idx] = qn;
+            if (basis && slot < d.basis_slots) d.basis[(long long)slot * d.bstride + idx] = (double)qn;
             if (q32) q32[idx] = (float)qn;      // operand copy for the FP32 kernel product
             else if (op.p) put_op16(static_cast<_Float16*>(op.p), op.nsbt, i, c, (double)qn, op.scale);
         }
@@ -688,6 +700,91 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
 template hipError_t launch_update<double>(const Dev&, const double*, long long, int, const double*, double*,
                                           const double*, double*, double*, double*, float*, int, hipStream_t,
                                           double*, Op16);
+
+// ----------------------------------------------------------------------------
+// Resident-basis combine. Per shift and column the logged coefficients give
+// the direction recurrence m_j = (q_j - delta_j m_{j-1} - eps_j m_{j-2}) ginv_j
+// and the weighted solution x = sum_j tauw_j m_j; expanding the highest m_j
+// first, x = sum_j c_j q_j with c_j = a_j ginv_j, where a_j = tauw_j plus what
+// the later terms pass down (-c_{j+1} delta_{j+1}, -c_{j+2} eps_{j+2}). A
+// frozen shift logs zeros from its freeze on, a stopped column stops at its
+// own iteration count, so both truncate the sums exactly as the recurrence
+// stops moving them.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void basis_coef_kernel(Dev d, int iters, double* __restrict__ cq) {
+    const int QN = d.Q * d.ncol;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= QN) return;
+    const int g = idx % d.ncol;
+    const int J = min(d.col_iters[g], iters);
+    const double* __restrict__ log = d.clog;
+    double r1 = 0.0, r2 = 0.0;
+    for (int j = J; j >= 1; --j) {
+        const double* lg = log + ((long long)(j - 1) * QN + idx) * 4;
+        const double c = (lg[3] + r1) * lg[2];
+        cq[(long long)(j - 1) * QN + idx] = c;
+        r1 = r2 - c * lg[0];
+        r2 = -c * lg[1];
+    }
+}
+
+// c[j][g] = sum over shifts of cq[j][q][g] (in shift order); 0 past the column's run
+__global__ __launch_bounds__(256) void basis_csum_kernel(Dev d, int iters, const double* __restrict__ cq,
+                                                         double* __restrict__ c) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)iters * d.ncol) return;
+    const int j = (int)(e / d.ncol), g = (int)(e - (long long)j * d.ncol);
+    double t = 0.0;
+    if (j < d.col_iters[g]) {
+        const double* row = cq + (long long)j * d.Q * d.ncol + g;
+        for (int q = 0; q < d.Q; ++q) t += row[(long long)q * d.ncol];
+    }
+    c[e] = t;
+}
+
+// acc[i][c] = sum_j c[j][g] q_{j+1}[i][c] (slot j), j ascending; eight slots'
+// loads in flight per step
+__global__ __launch_bounds__(256) void basis_gemv_kernel(Dev d, const double* __restrict__ c,
+                                                         double* __restrict__ acc) {
+    const int p = blockIdx.z;
+    const int n = d.n[p], off = d.row_off[p], s = d.s;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * s) return;
+    const int i = (int)(e / s), cc = (int)(e - (long long)i * s);
+    const int g = p * s + cc;
+    const long long idx = (long long)(off + i) * s + cc;
+    const int J = min(d.col_iters[g], d.basis_slots);
+    const double* __restrict__ b = d.basis + idx;
+    const double* __restrict__ cg = c + g;
+    const long long bs = d.bstride, cs = d.ncol;
+    double t = 0.0;
+    int j = 0;
+    for (; j + 8 <= J; j += 8) {
+        double v[8], w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[u] = __builtin_nontemporal_load(b + (long long)(j + u) * bs);
+            w[u] = cg[(long long)(j + u) * cs];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t = fma(w[u], v[u], t);
+    }
+    for (; j < J; ++j) t = fma(cg[(long long)j * cs], b[(long long)j * bs], t);
+    acc[idx] = t;
+}
+
+hipError_t launch_basis_combine(const Dev& d, int iters, double* cq, double* c, double* acc, int max_n,
+                                hipStream_t st) {
+    if (iters <= 0 || d.basis == nullptr || d.clog == nullptr) return hipErrorInvalidValue;
+    const int QN = d.Q * d.ncol;
+    hipLaunchKernelGGL(basis_coef_kernel, dim3((QN + 255) / 256), dim3(256), 0, st, d, iters, cq);
+    const long long ce = (long long)iters * d.ncol;
+    hipLaunchKernelGGL(basis_csum_kernel, dim3((unsigned)((ce + 255) / 256)), dim3(256), 0, st, d, iters, cq, c);
+    const long long ge = (long long)max_n * d.s;
+    hipLaunchKernelGGL(basis_gemv_kernel, dim3((unsigned)((ge + 255) / 256), 1, d.nprob), dim3(256), 0, st, d, c,
+                       acc);
+    return hipGetLastError();
+}
 
 // ----------------------------------------------------------------------------
 // Start of a run: q_1 = b / ||b|| (0 for a zero column), q_0 = 0, acc = 0.

@@ -53,8 +53,11 @@ class Problem:
         return p, arr  # keep arr alive with p
 
 
+BASIS_MODES = {"auto": 0, "off": 1}
+
+
 def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, check_every=0, profile=False,
-          kernel_cache="auto", cache_budget_mib=0, graph=False, precond_rank=0):
+          kernel_cache="auto", cache_budget_mib=0, graph=False, precond_rank=0, krylov_basis="auto"):
     o = L.ciq_opts()
     o.dtype = dtype_code
     o.q = int(q)
@@ -70,6 +73,7 @@ def _opts(dtype_code, q, max_iter, tol, lanczos_steps=0, seed=0, bounds=None, ch
     o.cache_budget_mib = int(cache_budget_mib)
     o.graph = 1 if graph else 0
     o.precond_rank = int(precond_rank)
+    o.krylov_basis = BASIS_MODES[krylov_basis]
     return o
 
 
@@ -147,7 +151,7 @@ def ciq_eig_bounds(problem: Problem, steps: int = 20, v0: Optional[torch.Tensor]
 
 
 def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves, lanczos_steps, seed,
-           check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank):
+           check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank, krylov_basis="auto"):
     lib = L.load()
     code = _dtype_code(problem.x, precision)
     b2 = b if b.dim() == 2 else b.reshape(-1, 1)
@@ -158,7 +162,7 @@ def _solve(fn_name, problem, b, q, max_iter, tol, precision, bounds, keep_solves
     solves = torch.empty((n, q, s), dtype=_elem_dtype(code), device=b.device) if keep_solves else None
     p, keep = problem.c_struct()
     o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, kernel_cache,
-              cache_budget_mib, graph, precond_rank)
+              cache_budget_mib, graph, precond_rank, krylov_basis)
     info = L.ciq_info()
     fn = getattr(lib, fn_name)
     L.check(fn(ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s, b2.stride(0),
@@ -173,22 +177,24 @@ def ciq_invsqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: in
                     precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
                     lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
                     kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False,
-                    precond_rank: int = 0):
+                    precond_rank: int = 0, krylov_basis: str = "auto"):
     """K^{-1/2} B -> (out, info, solves or None). With precond_rank > 0 the
     output is R' B, R' R'^T = K^{-1} (K^{-1/2} B up to a rotation)."""
     return _solve("ciq_invsqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank,
+                  krylov_basis)
 
 
 def ciq_sqrt_mvm(problem: Problem, b: torch.Tensor, q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                  precision: Optional[str] = None, bounds=None, keep_solves: bool = False,
                  lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
                  kernel_cache: str = "auto", cache_budget_mib: int = 0, graph: bool = False,
-                 precond_rank: int = 0):
+                 precond_rank: int = 0, krylov_basis: str = "auto"):
     """K^{1/2} B -> (out, info, solves or None). With precond_rank > 0 the
     output is R B, R R^T = K (K^{1/2} B up to a rotation)."""
     return _solve("ciq_sqrt_mvm", problem, b, q, max_iter, tol, precision, bounds, keep_solves,
-                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank)
+                  lanczos_steps, seed, check_every, profile, kernel_cache, cache_budget_mib, graph, precond_rank,
+                  krylov_basis)
 
 
 def ciq_posterior_mvm(candidates: Problem, x_obs: torch.Tensor, obs_noise: float, b: torch.Tensor,

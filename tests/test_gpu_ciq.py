@@ -227,6 +227,45 @@ def test_fp32_matches_fp64_oracle(kind, n, s, d, cache):
         assert err < 1e-4, (mode, err, info["iters"])
 
 
+@pytest.mark.parametrize("prec,cache", [("f64", "off"), ("f64", "on"), ("f32", "on")])
+def test_krylov_basis_matches_direction_recurrence(prec, cache):
+    """The resident Lanczos basis (solution formed once from the logged
+    direction coefficients) against the direction recurrence, same inputs and
+    bounds, both modes, ragged sizes, a zero column, columns stopping at
+    different iterations: the same iterate up to rounding."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(31)
+    n, d, s = 2345, 4, 19
+    dt = np.float64 if prec == "f64" else np.float32
+    x = rng.random((n, d)).astype(dt)
+    b = rng.standard_normal((n, s)).astype(dt)
+    b[:, 3] = 0.0
+    b[:, 5] *= 1e-4
+    K = okern.kernel_matrix("matern52", x.astype(np.float64), [0.35], 1.1, 2e-3)
+    lam = np.linalg.eigvalsh(K)
+    bounds = (lam[0], lam[-1])
+    announce(f"krylov basis vs recurrence {prec} cache={cache}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), "matern52", [0.35], 1.1, 2e-3)
+    bt = torch.from_numpy(b).cuda()
+    for mode, fn in [("invsqrt", ciq.ciq_invsqrt_mvm), ("sqrt", ciq.ciq_sqrt_mvm)]:
+        kw = dict(q=12, max_iter=3000, tol=1e-9 if prec == "f64" else 1e-6, bounds=bounds, kernel_cache=cache)
+        on, ion, _ = fn(prob, bt, krylov_basis="auto", **kw)
+        off, ioff, _ = fn(prob, bt, krylov_basis="off", **kw)
+        assert ion["krylov_basis"] and not ioff["krylov_basis"]
+        assert ion["iters"] == ioff["iters"] and ion["converged"] and ioff["converged"]
+        on, off = on.double().cpu().numpy(), off.double().cpu().numpy()
+        assert np.all(on[:, 3] == 0.0) and np.all(off[:, 3] == 0.0)
+        keep = [c for c in range(s) if c != 3]
+        gap = colwise_rel(on[:, keep], off[:, keep]).max()
+        ref, _ = ociq.ciq(lambda v: K @ v, b.astype(np.float64), bounds[0], bounds[1], 12, 3000, 1e-11, mode)
+        err_on = colwise_rel(on[:, keep], ref[:, keep]).max()
+        err_off = colwise_rel(off[:, keep], ref[:, keep]).max()
+        print(f"{prec} {mode}: basis vs recurrence {gap:.2e}; vs oracle {err_on:.2e} / {err_off:.2e}", flush=True)
+        assert gap < (1e-9 if prec == "f64" else 1e-6), gap
+        assert err_on <= 1.5 * err_off + 1e-12
+
+
 @pytest.mark.parametrize("s", [16, 32])
 def test_fp32_resident_inverse_root_has_no_accumulation_error(s):
     """The FP32 resident inverse root at <= 32 columns contracts the FP32
