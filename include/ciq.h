@@ -173,13 +173,17 @@ typedef struct ciq_opts {
     int32_t krylov_basis;      /* CIQ_BASIS_AUTO: when the run has neither a
                                   preconditioner nor kept per-shift solves and
                                   (max_iter + 1) Lanczos vectors fit in device
-                                  memory, keep them all resident (allocated and
-                                  freed inside the call) and form the solution
-                                  once after the run from the logged direction
-                                  coefficients, instead of moving Q direction
-                                  vectors every iteration (the same result up to
-                                  rounding). CIQ_BASIS_OFF: the direction
-                                  recurrence.                                    */
+                                  memory, keep the vectors the run reaches
+                                  resident and form the solution once after the
+                                  run from the logged direction coefficients,
+                                  instead of moving Q direction vectors every
+                                  iteration (the same result up to rounding).
+                                  The vectors live in 2 GiB chunks that stay
+                                  allocated on the device after the call for
+                                  the next one (ciq_release_workspace returns
+                                  them); a chunk the device cannot supply in the
+                                  middle of a run ends it with CIQ_ENOMEM.
+                                  CIQ_BASIS_OFF: the direction recurrence.       */
     int32_t reserved;
 } ciq_opts;
 
@@ -212,6 +216,19 @@ int ciq_version(void);
 
 /* Name of a status code (static string, never NULL). */
 const char* ciq_strerror(int status);
+
+/*
+ * Frees the device memory the library keeps on `device` between calls: the
+ * chunks of the resident Krylov basis and their coefficient logs
+ * (ciq_opts.krylov_basis), and the grow-only iteration scratch. Later calls
+ * allocate again what they need. The library also returns the basis chunks by
+ * itself when a later allocation would not fit beside them. Waits for a call
+ * running on that device in another thread to end, then for the device to
+ * drain. Leaves the current device unchanged.
+ * Errors: CIQ_EINVAL for a device index out of range; CIQ_EHIP if the runtime
+ * fails.
+ */
+int ciq_release_workspace(int device);
 
 /*
  * Hale-Higham-Trefethen quadrature for K^{-1/2} on [lambda_min, lambda_max]
@@ -445,8 +462,9 @@ int ciq_svgp_ngd_step(int M, int nb, const double* a, const double* mean, const 
  * msMINRES-CIQ exactly as ciq_sqrt_mvm / ciq_invsqrt_mvm do for K. Every
  * product with Sigma is the candidate kernel product (on the fly or resident,
  * any dtype) plus the FP64 low-rank correction -W (W^T v), W = Ksx L^{-T}
- * with L L^T = Kxx + obs_noise I factored once per call on the host (so
- * n_obs <= CIQ_MAX_OBS; the correction costs O(T n_obs s) per product). The
+ * with L L^T = Kxx + obs_noise I factored once per call on the device
+ * (blocked Cholesky and triangular solve on FP64 MFMA; n_obs <= CIQ_MAX_OBS;
+ * the correction costs O(T n_obs s) per product). The
  * eigenvalue floor is the jitter (Sigma - jitter I is a covariance).
  *   x_obs: device, n_obs x cand->d, same element type as cand->x.
  *   b, out, s, ldb, ldo, o, info: as for ciq_sqrt_mvm (no per-shift solves).

@@ -16,6 +16,7 @@ from .ops import (  # noqa: F401
     ciq_kernel_mvm_resident,
     ciq_pivoted_cholesky,
     ciq_posterior_mvm,
+    ciq_release_workspace,
     ciq_setup,
     ciq_sqrt_mvm,
     ciq_svgp_ngd_step,

@@ -121,6 +121,7 @@ _PD = ctypes.POINTER(ctypes.c_double)
 PROTOTYPES = {
     "ciq_version": (_I, []),
     "ciq_strerror": (ctypes.c_char_p, [_I]),
+    "ciq_release_workspace": (_I, [_I]),
     "ciq_setup": (_I, [_D, _D, _I, _PD, _PD]),
     "ciq_kernel_mvm": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),
     "ciq_kernel_mvm_resident": (_I, [ctypes.POINTER(ciq_problem), _I, _VP, _I, _I, _VP, _I, _VP]),

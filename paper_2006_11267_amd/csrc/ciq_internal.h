@@ -73,8 +73,7 @@ struct Dev {
     // q_{j+1} in slot j instead of moving the per-shift directions, and the
     // combination sum_j c_j q_j is formed once after the run
     double* clog;           // [max_iter][Q * ncol][4]: delta, eps, ginv, tauw
-    double* basis;          // [basis_slots][rows_total * s]: slot k holds q_{k+1}
-    long long bstride;      // elements per slot (rows_total * s)
+    double* const* basis;   // [basis_slots] slot pointers, rows_total * s doubles each: slot k holds q_{k+1}
     int basis_slots;
 };
 

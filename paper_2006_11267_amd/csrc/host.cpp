@@ -59,6 +59,117 @@ struct DeviceScratch {
 };
 DeviceScratch g_scratch[kMaxDevices];
 
+// ---- Krylov basis chunks kept between calls ---------------------------------
+// The resident basis takes up to max_iter + 1 vectors of rows_total * s
+// doubles (154 GB at N = 50,000, s = 64, 6000 iterations). Freeing a block
+// of tens of GB and allocating the next has been measured to take about two
+// seconds each on some driver states, so the slots live in fixed-size chunks
+// that stay allocated on the device after a call; the next call reuses them,
+// and a run takes new chunks only as its iteration count reaches them (the
+// memory held is what the longest run used). The coefficient logs of the
+// combine live in one grow-only buffer beside them. Guarded by the device's
+// scratch lock; ciq_release_workspace returns all of it.
+struct BasisPool {
+    std::vector<void*> chunks;
+    size_t chunk_bytes = 0;
+    void* logs = nullptr;
+    size_t logs_cap = 0;
+};
+BasisPool g_basis[kMaxDevices];
+
+// Frees the pool of the current device `dev` (after the device drains).
+int basis_pool_release(int dev) {
+    BasisPool& bp = g_basis[dev];
+    if (bp.chunks.empty() && !bp.logs) return CIQ_OK;
+    HIPCHK(hipDeviceSynchronize());
+    hipError_t e = hipSuccess;
+    for (void* c : bp.chunks) {
+        const hipError_t f = hipFree(c);
+        if (f != hipSuccess) e = f;
+    }
+    bp.chunks.clear();
+    if (bp.logs) {
+        const hipError_t f = hipFree(bp.logs);
+        if (f != hipSuccess) e = f;
+    }
+    bp.logs = nullptr;
+    bp.logs_cap = 0;
+    HIPCHK(e);
+    return CIQ_OK;
+}
+
+// hipMalloc on the current device; when the device is short it first returns
+// the basis chunks kept from earlier calls and tries once more.
+bool dev_malloc(void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *p = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (g_basis[dev].chunks.empty() && !g_basis[dev].logs) return false;
+    if (basis_pool_release(dev) != CIQ_OK) return false;
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+}
+
+// Chunk size: 2 GiB ($CIQ_BASIS_CHUNK_MIB overrides it), at least one slot.
+size_t basis_chunk_bytes(size_t stride) {
+    size_t mib = 2048;
+    if (const char* e = std::getenv("CIQ_BASIS_CHUNK_MIB")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v > 0) mib = (size_t)v;
+    }
+    const size_t c = std::max(mib << 20, stride);
+    return (c + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
+}
+
+// One run's slots: slot k is chunk k / per_chunk at byte offset
+// (k % per_chunk) * stride. `tab` (device, max_slots entries) holds the
+// pointers of the first `cap` slots; ensure() extends it, taking pooled
+// chunks first and allocating new ones past them, and is called before the
+// launches that can reach a slot. The host copy is sized once and only
+// appended to, so the stream-ordered copies can read it until the call ends.
+struct BasisSlots {
+    int dev = 0;
+    size_t stride = 0;
+    int per_chunk = 0;
+    int max_slots = 0;
+    int cap = 0;
+    std::vector<double*> host_tab;
+    double** tab = nullptr;
+
+    int ensure(int slots, hipStream_t st) {
+        slots = std::min(slots, max_slots);
+        if (slots <= cap) return CIQ_OK;
+        BasisPool& bp = g_basis[dev];
+        const int first = cap;
+        while (cap < slots) {
+            const size_t k = (size_t)cap / per_chunk;
+            if (k >= bp.chunks.size()) {
+                void* p = nullptr;
+                if (hipMalloc(&p, bp.chunk_bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return CIQ_ENOMEM;
+                }
+                bp.chunks.push_back(p);
+            }
+            char* base = static_cast<char*>(bp.chunks[k]);
+            const int end = (int)std::min<size_t>((k + 1) * per_chunk, (size_t)max_slots);
+            for (int t = cap; t < end; ++t)
+                host_tab[t] = reinterpret_cast<double*>(base + (size_t)(t - (int)(k * per_chunk)) * stride);
+            cap = end;
+        }
+        HIPCHK(hipMemcpyAsync(tab + first, host_tab.data() + first, (size_t)(cap - first) * sizeof(double*),
+                              hipMemcpyHostToDevice, st));
+        return CIQ_OK;
+    }
+};
+
 int scratch_reserve(int dev, size_t bytes, void** out) {
     DeviceScratch& sc = g_scratch[dev];
     if (sc.cap < bytes) {
@@ -72,7 +183,7 @@ int scratch_reserve(int dev, size_t bytes, void** out) {
         if (hipMalloc(&sc.ptr, want) != hipSuccess) {
             (void)hipGetLastError();
             sc.ptr = nullptr;
-            if (hipMalloc(&sc.ptr, bytes) != hipSuccess) {
+            if (!dev_malloc(&sc.ptr, bytes)) {
                 (void)hipGetLastError();
                 sc.ptr = nullptr;
                 return CIQ_ENOMEM;
@@ -375,7 +486,7 @@ int pc_build(const ciq_problem& p, const double* xh, int dp, int kernel, int ard
         return L;
     };
     layout(nullptr);
-    if (hipMalloc(&pc.mem.p, off) != hipSuccess) {
+    if (!dev_malloc(&pc.mem.p, off)) {
         (void)hipGetLastError();
         pc.mem.p = nullptr;
         return CIQ_ENOMEM;
@@ -461,7 +572,7 @@ int post_build(const ciq_problem& cand, int dtype, const double* xh, int dp, int
         po.T = carve<double>(base, off, (size_t)n * s_cap);
     };
     layout(nullptr);
-    if (hipMalloc(&po.mem.p, off) != hipSuccess) {
+    if (!dev_malloc(&po.mem.p, off)) {
         (void)hipGetLastError();
         po.mem.p = nullptr;
         return CIQ_ENOMEM;
@@ -507,6 +618,7 @@ struct Run {
     bool cached = false;   // products stream a resident kernel matrix (kt)
     bool precond = false;  // preconditioned run (single problem): Lanczos in the P^{-1} inner product
     const Precond* pc = nullptr;
+    BasisSlots* bslots = nullptr;   // resident Krylov basis of this run (d.basis is its table)
     const Posterior* post = nullptr;   // products with a posterior covariance (single problem)
     const SparseOp* sp = nullptr;      // products with a caller's sparse operator (single problem, FP64)
     const DenseOp* dn = nullptr;       // products with a dense operator (single-shift solves, FP64)
@@ -866,9 +978,11 @@ struct Run {
         if (solves) HIPCHK(launch_fill<double>(solves, (size_t)rows_total * s * Q, 0.0, st));
         HIPCHK(launch_init_vectors<double>(d, qbuf[0], qbuf[1], acc, q32, rows_total, st,
                                            precond ? pbuf[0] : nullptr, op16()));
-        if (d.basis)   // slot 0: q_1
-            HIPCHK(hipMemcpyAsync(d.basis, qbuf[0], (size_t)rows_total * s * sizeof(double), hipMemcpyDeviceToDevice,
-                                  st));
+        if (bslots) {   // slot 0: q_1
+            STCHK(bslots->ensure(1, st));
+            HIPCHK(hipMemcpyAsync(bslots->host_tab[0], qbuf[0], (size_t)rows_total * s * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+        }
         if (use_graph && ev_pool == nullptr) {
             hipStream_t cs = nullptr;
             hipGraph_t graph = nullptr;
@@ -894,6 +1008,7 @@ struct Run {
             const int per_poll = std::max(1, check_every / 2);
             int launched = 0;   // graph launches (2 iterations each)
             while (2 * launched < max_iter) {
+                if (bslots) STCHK(bslots->ensure(2 * launched + 3, st));   // slots up to iteration 2 launched + 2
                 HIPCHK(hipGraphLaunch(exec, st));
                 ++launched;
                 if (launched % per_poll == 0 || 2 * launched >= max_iter) {
@@ -909,6 +1024,7 @@ struct Run {
             int pending = 0;
             while (j <= max_iter) {
                 const bool timed = ev_pool != nullptr && pending < n_ev;
+                if (bslots) STCHK(bslots->ensure(j + 1, st));   // slots 0..j
                 if (timed) HIPCHK(hipEventRecord(ev_pool[2 * pending], st));
                 STCHK(product(j, st));
                 if (timed) {
@@ -1101,11 +1217,19 @@ int kcache_acquire(const ciq_opts* o, int dtype, int nprob, const ciq_problem* p
     if (o->kernel_cache != CIQ_CACHE_ON) {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
+        if (bytes > fr / 2) {   // basis chunks kept from earlier calls give way to the matrix
+            int dev = 0;
+            HIPCHK(hipGetDevice(&dev));
+            if (!g_basis[dev].chunks.empty()) {
+                STCHK(basis_pool_release(dev));
+                HIPCHK(hipMemGetInfo(&fr, &tot));
+            }
+        }
         size_t limit = fr / 2;
         if (o->cache_budget_mib > 0) limit = std::min(limit, (size_t)o->cache_budget_mib << 20);
         if (bytes > limit) return CIQ_OK;
     }
-    if (hipMalloc(&kc.ptr, bytes) != hipSuccess) {
+    if (!dev_malloc(&kc.ptr, bytes)) {
         (void)hipGetLastError();
         kc.ptr = nullptr;
         return o->kernel_cache == CIQ_CACHE_ON ? CIQ_ENOMEM : CIQ_OK;
@@ -1352,33 +1476,72 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         STCHK(tune_rt(main, main.qbuf[0], st));
     }
 
-    // ---- resident Krylov basis (when it fits; allocated for this call) -----
-    DevAlloc basis_mem;
+    // ---- resident Krylov basis (when every slot the run may reach fits) -----
+    BasisSlots bslots;
     double *basis_cq = nullptr, *basis_c = nullptr;
     bool use_basis = false;
     if (o->krylov_basis == CIQ_BASIS_AUTO && !precond && solves_out == nullptr && main.Q > 0) {
+        BasisPool& bp = g_basis[dev];
         const size_t slots = (size_t)main.max_iter + 1;
-        const size_t vec = (size_t)main.rows_total * s;
+        const size_t stride = ((size_t)main.rows_total * s * sizeof(double) + 255) & ~size_t(255);
+        const size_t chunk = basis_chunk_bytes(stride);
+        if (bp.chunk_bytes != chunk) {   // another chunk size: start the pool over
+            STCHK(basis_pool_release(dev));
+            bp.chunk_bytes = chunk;
+        }
+        const size_t per_chunk = chunk / stride;
+        const size_t chunks = (slots + per_chunk - 1) / per_chunk;
         const size_t qn = (size_t)main.Q * main.d.ncol;
         const size_t iters_cap = (size_t)main.max_iter;
-        const size_t bytes =
-            (slots * vec + iters_cap * qn * 4 + iters_cap * qn + iters_cap * main.d.ncol) * sizeof(double) + 4 * 256;
+        auto log_layout = [&](auto& c) {   // coefficient logs and the slot table
+            main.d.clog = c.template take<double>(iters_cap * qn * 4);
+            basis_cq = c.template take<double>(iters_cap * qn);
+            basis_c = c.template take<double>(iters_cap * main.d.ncol);
+            bslots.tab = c.template take<double*>(slots);
+        };
+        Sizer lz;
+        log_layout(lz);
+        const size_t logs = lz.off;
+        const size_t more =
+            (chunks > bp.chunks.size() ? (chunks - bp.chunks.size()) * chunk : 0) + (logs > bp.logs_cap ? logs : 0);
         size_t free_b = 0, total_b = 0;
         // leave a tenth of the free memory and 4 GiB for everything else
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes + (size_t(4) << 30) <= free_b / 10 * 9 &&
-            hipMalloc(&basis_mem.p, bytes) == hipSuccess) {
-            size_t off = 0;
-            char* base = static_cast<char*>(basis_mem.p);
-            main.d.basis = carve<double>(base, off, slots * vec);
-            main.d.clog = carve<double>(base, off, iters_cap * qn * 4);
-            basis_cq = carve<double>(base, off, iters_cap * qn);
-            basis_c = carve<double>(base, off, iters_cap * main.d.ncol);
-            main.d.bstride = (long long)vec;
+        bool fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess && more + (size_t(4) << 30) <= free_b / 10 * 9;
+        if (!fits) (void)hipGetLastError();
+        if (fits && logs > bp.logs_cap) {
+            if (bp.logs) {
+                HIPCHK(hipDeviceSynchronize());
+                HIPCHK(hipFree(bp.logs));
+                bp.logs = nullptr;
+                bp.logs_cap = 0;
+            }
+            if (hipMalloc(&bp.logs, logs) == hipSuccess) {
+                bp.logs_cap = logs;
+            } else {
+                (void)hipGetLastError();
+                bp.logs = nullptr;
+                fits = false;
+            }
+        }
+        if (fits) {
+            Carver lc(bp.logs);
+            log_layout(lc);
+            bslots.dev = dev;
+            bslots.stride = stride;
+            bslots.per_chunk = (int)per_chunk;
+            bslots.max_slots = (int)slots;
+            bslots.host_tab.assign(slots, nullptr);
+            HIPCHK(launch_fill<double>(reinterpret_cast<double*>(bslots.tab), slots, 0.0, st));   // null pointers
+            // the pooled chunks at once (one table copy); the run takes new ones as it reaches them
+            STCHK(bslots.ensure((int)std::min(bp.chunks.size() * per_chunk, slots), st));
+            main.d.basis = bslots.tab;
             main.d.basis_slots = (int)slots;
+            main.bslots = &bslots;
             use_basis = true;
         } else {
-            (void)hipGetLastError();
-            basis_mem.p = nullptr;
+            main.d.clog = nullptr;
+            basis_cq = basis_c = nullptr;
+            bslots.tab = nullptr;
         }
     }
 
@@ -1732,6 +1895,26 @@ const char* ciq_strerror(int status) {
     }
 }
 
+int ciq_release_workspace(int device) {
+    if (device < 0 || device >= kMaxDevices) return CIQ_EINVAL;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device >= ndev) return CIQ_EINVAL;
+    ScratchLock lock(device);
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) HIPCHK(hipSetDevice(device));
+    int rc = basis_pool_release(device);
+    DeviceScratch& sc = g_scratch[device];
+    if (rc == CIQ_OK && sc.ptr) {
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(sc.ptr) != hipSuccess) rc = CIQ_EHIP;
+        sc.ptr = nullptr;
+        sc.cap = 0;
+    }
+    if (cur != device && hipSetDevice(cur) != hipSuccess && rc == CIQ_OK) rc = CIQ_EHIP;
+    return rc;
+}
+
 int ciq_setup(double lambda_min, double lambda_max, int q, double* t_out, double* w_out) {
     if (!t_out || !w_out || q < 1 || q > CIQ_MAX_Q) return CIQ_EINVAL;
     if (!(lambda_min > 0.0) || !(lambda_max >= lambda_min) || !std::isfinite(lambda_max)) return CIQ_EINVAL;
@@ -2019,7 +2202,7 @@ int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* 
         }
     };
     layout(nullptr);
-    if (hipMalloc(&mem.p, off) != hipSuccess) {
+    if (!dev_malloc(&mem.p, off)) {
         (void)hipGetLastError();
         mem.p = nullptr;
         return CIQ_ENOMEM;
@@ -2127,7 +2310,7 @@ int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_ou
         pchol_layout(n, rank, [&](size_t c) { return carve<double>(base, off, c); }, w);
     };
     layout(nullptr);
-    if (hipMalloc(&mem.p, off) != hipSuccess) {
+    if (!dev_malloc(&mem.p, off)) {
         (void)hipGetLastError();
         mem.p = nullptr;
         return CIQ_ENOMEM;

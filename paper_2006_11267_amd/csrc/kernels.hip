@@ -580,6 +580,7 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
     const bool basis = d.basis != nullptr;
     const int Q = basis ? 0 : d.Q;
     const int slot = d.st->iter;
+    double* const bq = (basis && slot < d.basis_slots) ? d.basis[slot] : nullptr;
     T* sdelta = reinterpret_cast<T*>(smem);
     T* seps = sdelta + Q * TS;
     T* sginv = seps + Q * TS;
@@ -642,7 +643,7 @@ __global__ __launch_bounds__(256) void update_kernel(Dev d, const T* y, long lon
             const T v = vT - al * qj;
             const T qn = v * ib;
             qprev[idx] = qn;
-            if (basis && slot < d.basis_slots) d.basis[(long long)slot * d.bstride + idx] = (double)qn;
+            if (bq) bq[idx] = (double)qn;
             if (q32) q32[idx] = (float)qn;      // operand copy for the FP32 kernel product
             else if (op.p) put_op16(static_cast<_Float16*>(op.p), op.nsbt, i, c, (double)qn, op.scale);
         }
@@ -742,8 +743,8 @@ __global__ __launch_bounds__(256) void basis_csum_kernel(Dev d, int iters, const
     c[e] = t;
 }
 
-// acc[i][c] = sum_j c[j][g] q_{j+1}[i][c] (slot j), j ascending; eight slots'
-// loads in flight per step
+// acc[i][c] = sum_j c[j][g] q_{j+1}[i][c] (slot j, through the slot table),
+// j ascending; eight slots' loads in flight per step
 __global__ __launch_bounds__(256) void basis_gemv_kernel(Dev d, const double* __restrict__ c,
                                                          double* __restrict__ acc) {
     const int p = blockIdx.z;
@@ -754,22 +755,22 @@ __global__ __launch_bounds__(256) void basis_gemv_kernel(Dev d, const double* __
     const int g = p * s + cc;
     const long long idx = (long long)(off + i) * s + cc;
     const int J = min(d.col_iters[g], d.basis_slots);
-    const double* __restrict__ b = d.basis + idx;
+    double* const* __restrict__ tab = d.basis;
     const double* __restrict__ cg = c + g;
-    const long long bs = d.bstride, cs = d.ncol;
+    const long long cs = d.ncol;
     double t = 0.0;
     int j = 0;
     for (; j + 8 <= J; j += 8) {
         double v[8], w[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            v[u] = __builtin_nontemporal_load(b + (long long)(j + u) * bs);
+            v[u] = __builtin_nontemporal_load(tab[j + u] + idx);
             w[u] = cg[(long long)(j + u) * cs];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) t = fma(w[u], v[u], t);
     }
-    for (; j < J; ++j) t = fma(cg[(long long)j * cs], b[(long long)j * bs], t);
+    for (; j < J; ++j) t = fma(cg[(long long)j * cs], tab[j][idx], t);
     acc[idx] = t;
 }
 

@@ -81,6 +81,14 @@ def ciq_version() -> int:
     return L.load().ciq_version()
 
 
+def ciq_release_workspace(device: Optional[int] = None) -> None:
+    """Free the device memory the library keeps between calls (resident Krylov
+    basis chunks, their logs, the iteration scratch) on `device` (default: the
+    current one)."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    L.check(L.load().ciq_release_workspace(dev), "ciq_release_workspace")
+
+
 def ciq_setup(lambda_min: float, lambda_max: float, q: int):
     """HHT shifts t (ascending) and weights w (host FP64)."""
     lib = L.load()

@@ -275,3 +275,9 @@ def test_strerror(lib):
     for code in range(6):
         assert lib.ciq_strerror(code)
     assert b"unknown" in lib.ciq_strerror(99)
+
+
+def test_release_workspace_rejects_bad_devices(lib):
+    # range checks come before any runtime call
+    assert lib.ciq_release_workspace(-1) == L.CIQ_EINVAL
+    assert lib.ciq_release_workspace(64) == L.CIQ_EINVAL

@@ -266,6 +266,49 @@ def test_krylov_basis_matches_direction_recurrence(prec, cache):
         assert err_on <= 1.5 * err_off + 1e-12
 
 
+def test_krylov_basis_chunks_reused_across_calls(monkeypatch):
+    """The basis slots live in chunks kept between calls. With 2 MiB chunks
+    (five slots of n = 2345, s = 19) every run crosses many chunk boundaries
+    while it iterates; the calls in a row reuse the chunks of the earlier ones
+    (another problem size, the graph-replayed loop), a new chunk size starts
+    the pool over, and after ciq_release_workspace the next call allocates
+    afresh. Each result equals the direction recurrence's up to rounding."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    ciq.ciq_release_workspace()
+
+    def case(n, s, seed):
+        r = np.random.default_rng(seed)
+        x = r.random((n, 4))
+        b = r.standard_normal((n, s))
+        K = okern.kernel_matrix("matern52", x, [0.35], 1.1, 2e-3)
+        lam = np.linalg.eigvalsh(K)
+        prob = ciq.Problem(torch.from_numpy(x).cuda(), "matern52", [0.35], 1.1, 2e-3)
+        return prob, torch.from_numpy(b).cuda(), (lam[0], lam[-1])
+
+    big = case(2345, 19, 1)
+    small = case(1000, 7, 2)
+    steps = [("1", big, False, ciq.ciq_sqrt_mvm), ("1", big, True, ciq.ciq_invsqrt_mvm),
+             ("1", small, False, ciq.ciq_sqrt_mvm), ("3", big, False, ciq.ciq_invsqrt_mvm),
+             ("release", big, True, ciq.ciq_sqrt_mvm)]
+    for chunk_mib, (prob, bt, bounds), graph, fn in steps:
+        if chunk_mib == "release":
+            ciq.ciq_release_workspace()
+        else:
+            monkeypatch.setenv("CIQ_BASIS_CHUNK_MIB", chunk_mib)
+        announce(f"krylov basis chunks {chunk_mib} n={bt.shape[0]} s={bt.shape[1]} graph={graph} {fn.__name__}")
+        kw = dict(q=12, max_iter=3000, tol=1e-9, bounds=bounds, kernel_cache="on", graph=graph)
+        on, ion, _ = fn(prob, bt, krylov_basis="auto", **kw)
+        off, ioff, _ = fn(prob, bt, krylov_basis="off", **kw)
+        assert ion["krylov_basis"] and not ioff["krylov_basis"]
+        assert ion["converged"] and ion["iters"] == ioff["iters"] and ion["iters"] > 50
+        gap = colwise_rel(on.cpu().numpy(), off.cpu().numpy()).max()
+        print(f"chunks {chunk_mib}: {ion['iters']} iterations, basis vs recurrence {gap:.2e}", flush=True)
+        assert gap < 1e-9, gap
+    monkeypatch.delenv("CIQ_BASIS_CHUNK_MIB")
+    ciq.ciq_release_workspace()
+
+
 @pytest.mark.parametrize("s", [16, 32])
 def test_fp32_resident_inverse_root_has_no_accumulation_error(s):
     """The FP32 resident inverse root at <= 32 columns contracts the FP32
