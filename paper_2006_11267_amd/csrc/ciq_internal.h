@@ -232,6 +232,15 @@ hipError_t launch_update(const Dev& d, const T* y, long long ysplit, int nsplit,
 
 // pvec (nullable): preconditioned start, pvec <- pvec / beta_1 too and q32
 // copies pvec instead of q.
+// Slot pointer table of the resident basis for slots [first, end), from the
+// bases of chunks k0 .. k0 + kBasisChunksPerLaunch - 1 (passed by value).
+constexpr int kBasisChunksPerLaunch = 16;
+struct BasisChunks {
+    char* base[kBasisChunksPerLaunch];
+};
+hipError_t launch_basis_table(double** tab, int first, int end, int per_chunk, size_t stride, int k0,
+                              const BasisChunks& c, hipStream_t st);
+
 // After a run with the resident basis: acc = sum_j c_j q_j per column, the
 // coefficients c_j by back-substitution of the logged direction recurrence
 // of every (shift, column). cq: [iters][Q * ncol], c: [iters][ncol] doubles

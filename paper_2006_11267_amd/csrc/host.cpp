@@ -130,42 +130,46 @@ size_t basis_chunk_bytes(size_t stride) {
 
 // One run's slots: slot k is chunk k / per_chunk at byte offset
 // (k % per_chunk) * stride. `tab` (device, max_slots entries) holds the
-// pointers of the first `cap` slots; ensure() extends it, taking pooled
-// chunks first and allocating new ones past them, and is called before the
-// launches that can reach a slot. The host copy is sized once and only
-// appended to, so the stream-ordered copies can read it until the call ends.
+// pointers of the first `cap` slots; ensure() extends it on the stream (a
+// small kernel writes the new entries), taking pooled chunks first and
+// allocating new ones past them. Called before the launches that can reach
+// a slot.
 struct BasisSlots {
     int dev = 0;
     size_t stride = 0;
     int per_chunk = 0;
     int max_slots = 0;
     int cap = 0;
-    std::vector<double*> host_tab;
     double** tab = nullptr;
+
+    double* slot(int t) const {
+        return reinterpret_cast<double*>(static_cast<char*>(g_basis[dev].chunks[(size_t)t / per_chunk]) +
+                                         (size_t)(t % per_chunk) * stride);
+    }
 
     int ensure(int slots, hipStream_t st) {
         slots = std::min(slots, max_slots);
         if (slots <= cap) return CIQ_OK;
         BasisPool& bp = g_basis[dev];
         const int first = cap;
-        while (cap < slots) {
-            const size_t k = (size_t)cap / per_chunk;
-            if (k >= bp.chunks.size()) {
-                void* p = nullptr;
-                if (hipMalloc(&p, bp.chunk_bytes) != hipSuccess) {
-                    (void)hipGetLastError();
-                    return CIQ_ENOMEM;
-                }
-                bp.chunks.push_back(p);
+        const size_t kend = ((size_t)slots + per_chunk - 1) / per_chunk;   // chunks that cover the slots
+        while (bp.chunks.size() < kend) {
+            void* p = nullptr;
+            if (hipMalloc(&p, bp.chunk_bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return CIQ_ENOMEM;
             }
-            char* base = static_cast<char*>(bp.chunks[k]);
-            const int end = (int)std::min<size_t>((k + 1) * per_chunk, (size_t)max_slots);
-            for (int t = cap; t < end; ++t)
-                host_tab[t] = reinterpret_cast<double*>(base + (size_t)(t - (int)(k * per_chunk)) * stride);
-            cap = end;
+            bp.chunks.push_back(p);
         }
-        HIPCHK(hipMemcpyAsync(tab + first, host_tab.data() + first, (size_t)(cap - first) * sizeof(double*),
-                              hipMemcpyHostToDevice, st));
+        cap = (int)std::min(kend * per_chunk, (size_t)max_slots);
+        for (size_t k0 = (size_t)first / per_chunk; k0 < kend; k0 += kBasisChunksPerLaunch) {
+            BasisChunks c{};
+            for (int u = 0; u < kBasisChunksPerLaunch && k0 + u < kend; ++u)
+                c.base[u] = static_cast<char*>(bp.chunks[k0 + u]);
+            const int lo = std::max(first, (int)(k0 * per_chunk));
+            const int hi = (int)std::min((k0 + kBasisChunksPerLaunch) * per_chunk, (size_t)cap);
+            HIPCHK(launch_basis_table(tab, lo, hi, per_chunk, stride, (int)k0, c, st));
+        }
         return CIQ_OK;
     }
 };
@@ -980,7 +984,7 @@ struct Run {
                                            precond ? pbuf[0] : nullptr, op16()));
         if (bslots) {   // slot 0: q_1
             STCHK(bslots->ensure(1, st));
-            HIPCHK(hipMemcpyAsync(bslots->host_tab[0], qbuf[0], (size_t)rows_total * s * sizeof(double),
+            HIPCHK(hipMemcpyAsync(bslots->slot(0), qbuf[0], (size_t)rows_total * s * sizeof(double),
                                   hipMemcpyDeviceToDevice, st));
         }
         if (use_graph && ev_pool == nullptr) {
@@ -1504,10 +1508,12 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
         const size_t logs = lz.off;
         const size_t more =
             (chunks > bp.chunks.size() ? (chunks - bp.chunks.size()) * chunk : 0) + (logs > bp.logs_cap ? logs : 0);
-        size_t free_b = 0, total_b = 0;
-        // leave a tenth of the free memory and 4 GiB for everything else
-        bool fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess && more + (size_t(4) << 30) <= free_b / 10 * 9;
-        if (!fits) (void)hipGetLastError();
+        bool fits = true;
+        if (more > 0) {   // leave a tenth of the free memory and 4 GiB for everything else
+            size_t free_b = 0, total_b = 0;
+            fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess && more + (size_t(4) << 30) <= free_b / 10 * 9;
+            if (!fits) (void)hipGetLastError();
+        }
         if (fits && logs > bp.logs_cap) {
             if (bp.logs) {
                 HIPCHK(hipDeviceSynchronize());
@@ -1530,9 +1536,8 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
             bslots.stride = stride;
             bslots.per_chunk = (int)per_chunk;
             bslots.max_slots = (int)slots;
-            bslots.host_tab.assign(slots, nullptr);
             HIPCHK(launch_fill<double>(reinterpret_cast<double*>(bslots.tab), slots, 0.0, st));   // null pointers
-            // the pooled chunks at once (one table copy); the run takes new ones as it reaches them
+            // the pooled chunks at once; the run takes new ones as it reaches them
             STCHK(bslots.ensure((int)std::min(bp.chunks.size() * per_chunk, slots), st));
             main.d.basis = bslots.tab;
             main.d.basis_slots = (int)slots;

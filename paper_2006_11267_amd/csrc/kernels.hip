@@ -774,6 +774,27 @@ __global__ __launch_bounds__(256) void basis_gemv_kernel(Dev d, const double* __
     acc[idx] = t;
 }
 
+// tab[t] for slots t in [first, end): slot t sits at byte offset
+// (t % per_chunk) * stride of chunk t / per_chunk, whose base is
+// c.base[t / per_chunk - k0] (every slot of the range lies in chunks
+// k0 .. k0 + kBasisChunksPerLaunch - 1)
+__global__ __launch_bounds__(256) void basis_table_kernel(double** __restrict__ tab, int first, int end,
+                                                          int per_chunk, long long stride, int k0, BasisChunks c) {
+    const int t = first + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= end) return;
+    const int k = t / per_chunk;
+    tab[t] = reinterpret_cast<double*>(c.base[k - k0] + (long long)(t - k * per_chunk) * stride);
+}
+
+hipError_t launch_basis_table(double** tab, int first, int end, int per_chunk, size_t stride, int k0,
+                              const BasisChunks& c, hipStream_t st) {
+    if (end <= first) return hipSuccess;
+    if (first / per_chunk < k0 || (end - 1) / per_chunk >= k0 + kBasisChunksPerLaunch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(basis_table_kernel, dim3((unsigned)((end - first + 255) / 256)), dim3(256), 0, st, tab, first,
+                       end, per_chunk, (long long)stride, k0, c);
+    return hipGetLastError();
+}
+
 hipError_t launch_basis_combine(const Dev& d, int iters, double* cq, double* c, double* acc, int max_n,
                                 hipStream_t st) {
     if (iters <= 0 || d.basis == nullptr || d.clog == nullptr) return hipErrorInvalidValue;

@@ -209,7 +209,7 @@ def ciq_posterior_mvm(candidates: Problem, x_obs: torch.Tensor, obs_noise: float
                       mode: str = "sqrt", q: int = 15, max_iter: int = 200, tol: float = 1e-4,
                       precision: Optional[str] = None, bounds=None, lanczos_steps: int = 0, seed: int = 0,
                       check_every: int = 0, profile: bool = False, kernel_cache: str = "auto",
-                      cache_budget_mib: int = 0, graph: bool = False):
+                      cache_budget_mib: int = 0, graph: bool = False, krylov_basis: str = "auto"):
     """Sigma^{1/2} B (mode "sqrt") or Sigma^{-1/2} B ("invsqrt") for the GP
     posterior covariance at the candidates given observations at x_obs
     (candidates.noise is the jitter) -> (out, info)."""
@@ -224,7 +224,7 @@ def ciq_posterior_mvm(candidates: Problem, x_obs: torch.Tensor, obs_noise: float
     out = torch.empty((n, s), dtype=_elem_dtype(code), device=b.device)
     p, keep = candidates.c_struct()
     o = _opts(code, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, kernel_cache,
-              cache_budget_mib, graph)
+              cache_budget_mib, graph, krylov_basis=krylov_basis)
     info = L.ciq_info()
     mode_code = L.CIQ_SQRT if mode == "sqrt" else L.CIQ_INVSQRT
     L.check(lib.ciq_posterior_mvm(ctypes.byref(p), ctypes.c_void_p(x_obs.data_ptr()), x_obs.shape[0],
@@ -238,7 +238,7 @@ def ciq_posterior_mvm(candidates: Problem, x_obs: torch.Tensor, obs_noise: float
 def ciq_csr_mvm(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, b: torch.Tensor,
                 mode: str = "invsqrt", q: int = 15, max_iter: int = 400, tol: float = 1e-4, bounds=None,
                 lanczos_steps: int = 0, seed: int = 0, check_every: int = 0, profile: bool = False,
-                graph: bool = False):
+                graph: bool = False, krylov_basis: str = "auto"):
     """A^{-1/2} B ("invsqrt") or A^{1/2} B ("sqrt") for a sparse symmetric
     positive-definite A given in CSR form (int32 indices, float64 values,
     device tensors) -> (out, info)."""
@@ -254,7 +254,8 @@ def ciq_csr_mvm(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor,
     out = torch.empty((n, s), dtype=torch.float64, device=b.device)
     a = L.ciq_csr(n=n, nnz=col_idx.numel(), row_ptr=ctypes.c_void_p(row_ptr.data_ptr()),
                   col_idx=ctypes.c_void_p(col_idx.data_ptr()), val=ctypes.c_void_p(val.data_ptr()))
-    o = _opts(L.CIQ_F64, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, graph=graph)
+    o = _opts(L.CIQ_F64, q, max_iter, tol, lanczos_steps, seed, bounds, check_every, profile, graph=graph,
+              krylov_basis=krylov_basis)
     info = L.ciq_info()
     mode_code = L.CIQ_SQRT if mode == "sqrt" else L.CIQ_INVSQRT
     L.check(lib.ciq_csr_mvm(ctypes.byref(a), mode_code, ctypes.byref(o), ctypes.c_void_p(b2.data_ptr()), s,
