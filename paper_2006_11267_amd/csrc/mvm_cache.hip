@@ -419,24 +419,27 @@ __device__ __forceinline__ void kt32_item(const MvmArgs& a, int p, int rb, int s
             }
         }
     };
-    // one chunk: publish its V rows, start later loads, contract; the B
-    // operands of step st + 1 are read from LDS before step st's MFMAs
+    // one chunk: publish its V rows in LDS buffer c % 2, start later loads,
+    // contract; the B operands of step st + 1 are read from LDS before step
+    // st's MFMAs. One barrier per chunk: a wave writes buffer c % 2 again only
+    // after the barrier of chunk c + 1, which every wave reaches after its
+    // reads of chunk c (the caller's barrier separates work items).
     auto chunk = [&](int c, float (&cur)[RT][16], float (&far)[RT][16]) {
-        __syncthreads();
+        float* vb = vs + (c & 1) * (BN * VST);
 #pragma unroll
-        for (int k = 0; k < VPV; ++k) *reinterpret_cast<VecT*>(&vs[(vr + k * VR) * VST + VW * vc]) = vreg[k];
+        for (int k = 0; k < VPV; ++k) *reinterpret_cast<VecT*>(&vb[(vr + k * VR) * VST + VW * vc]) = vreg[k];
         __syncthreads();
         if (c + 1 < c1) fetch_v(c + 1);
         if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
         float bcur[NSB], bnxt[NSB];
 #pragma unroll
-        for (int sb = 0; sb < NSB; ++sb) bcur[sb] = vs[(lane >> 4) * VST + sb * 16 + (lane & 15)];
+        for (int sb = 0; sb < NSB; ++sb) bcur[sb] = vb[(lane >> 4) * VST + sb * 16 + (lane & 15)];
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
             if (st + 1 < 16) {
                 const int jn = 4 * (st + 1) + (lane >> 4);
 #pragma unroll
-                for (int sb = 0; sb < NSB; ++sb) bnxt[sb] = vs[jn * VST + sb * 16 + (lane & 15)];
+                for (int sb = 0; sb < NSB; ++sb) bnxt[sb] = vb[jn * VST + sb * 16 + (lane & 15)];
             }
             if constexpr (F64M) {
 #pragma unroll
@@ -519,7 +522,7 @@ template <int NSB, int RT, int WAVES, int KD, int NACC>
 __global__ __launch_bounds__(64 * WAVES) void mvm_kt32_kernel(MvmArgs a) {
     constexpr int S16 = NSB * 16;
     constexpr int VST = (NSB & 1) ? S16 : S16 + 16;
-    __shared__ __attribute__((aligned(16))) float vs[64 * VST];
+    __shared__ __attribute__((aligned(16))) float vs[2 * 64 * VST];   // two chunk buffers
     __shared__ int item_sh;
     if (mfma::done_now(a.done)) return;
     if (a.queue != nullptr) {            // batched, persistent
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
     constexpr int VU = 2 * NSB * 128;            // 16-byte V units per chunk
     static_assert(VU % NT == 0, "V units per thread");
     constexpr int UPT = VU / NT;
-    __shared__ f16x8 vs[VU];
+    __shared__ f16x8 vs[2 * VU];   // two chunk buffers (one barrier per chunk, as in kt32_item)
 
     if (mfma::done_now(a.done)) return;
     const int nsplit = a.nsplit;
@@ -611,9 +614,9 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
                 dst[rt][p] = __builtin_nontemporal_load(kb[rt] + (size_t)c * 256 + (unsigned)(64 * p + lane));
     };
     auto chunk = [&](int c, f16x8 (&cur)[RT][4], f16x8 (&far)[RT][4]) {
-        __syncthreads();
+        f16x8* vb = vs + (c & 1) * VU;
 #pragma unroll
-        for (int m = 0; m < UPT; ++m) vs[tid + NT * m] = vreg[m];
+        for (int m = 0; m < UPT; ++m) vb[tid + NT * m] = vreg[m];
         __syncthreads();
         if (c + 1 < c1) fetch_v(c + 1);
         if (c + KD - 1 < c1) fetch_k(c + KD - 1, far);
@@ -621,8 +624,8 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
         for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
             for (int sb = 0; sb < NSB; ++sb) {
-                const f16x8 bh = vs[(kk * NSB + sb) * 128 + lane];
-                const f16x8 bl = vs[(kk * NSB + sb) * 128 + 64 + lane];
+                const f16x8 bh = vb[(kk * NSB + sb) * 128 + lane];
+                const f16x8 bl = vb[(kk * NSB + sb) * 128 + 64 + lane];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
                     ah[rt][sb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur[rt][2 * kk], bh, ah[rt][sb], 0, 0, 0);
