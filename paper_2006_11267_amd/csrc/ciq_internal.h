@@ -119,6 +119,8 @@ struct MvmArgs {
                              // FP32 path: raw coordinates, scaled after subtraction)
     const void* v;           // rows x s (ld = ldv); float (FP32 path) or double
     void* y;                 // double partial outputs: nsplit x rows x s (ld = ldy)
+    float* y32;              // set: the resident FP32 / split-FP16 products write their
+                             // partials here instead, rounded once to FP32 (same layout)
     long long ysplit;        // elements between split partials
     int ldv, ldy;
     int s;
@@ -212,9 +214,13 @@ template <typename TO>
 hipError_t launch_reduce_splits(const double* ypart, long long ysplit, int nsplit, int ldy,
                                 int n, int s, TO* out, int ldo, hipStream_t st);
 
+// Block partials of the inner products (phase 0: q_j^T (y - beta_j q_{j-1}),
+// reducing the nsplit product partials into y's first slot; phase 1:
+// ||y - beta_j q_{j-1} - alpha_j q_j||^2). y32 set (phase 0 only): the split
+// partials are FP32 there and are summed in FP64 into y's first slot.
 template <typename T>
 hipError_t launch_dots(const Dev& d, T* y, long long ysplit, int nsplit, const T* q,
-                       const T* qp, int phase, hipStream_t st);
+                       const T* qp, int phase, hipStream_t st, const float* y32 = nullptr);
 
 hipError_t launch_colsum(const Dev& d, int k, hipStream_t st);
 hipError_t launch_scalar_init(const Dev& d, hipStream_t st);

@@ -655,6 +655,11 @@ struct Run {
     double* opinv = nullptr;
     Dev d{};
     long long ysplit = 0;
+    // square root's main loop on a resident FP32 / split-FP16 matrix (one
+    // problem, no preconditioner, posterior or caller operator): the product
+    // writes FP32 split partials, which phase 0 sums in FP64 (see solve)
+    bool part32 = false;
+    float* ypart32 = nullptr;
     // host mirrors
     std::vector<int> h_n, h_off;
     std::vector<float> h_o2, h_s2;
@@ -671,6 +676,7 @@ struct Run {
         qbuf[0] = a.template take<double>(vec);
         qbuf[1] = a.template take<double>(vec);
         ypart = a.template take<double>(vec * nsplit_alloc);
+        if (part32) ypart32 = a.template take<float>(vec * nsplit_alloc);
         if (Q > 0) {
             mbuf[0] = a.template take<double>(vec * Q);
             mbuf[1] = a.template take<double>(vec * Q);
@@ -898,7 +904,8 @@ struct Run {
                                          pnxt, op16()));
             return CIQ_OK;
         }
-        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st));   // also reduces the splits
+        HIPCHK(launch_dots<double>(d, ypart, ysplit, nsplit, qcur, qprv, 0, st,   // also reduces the splits
+                                   (part32 && nsplit > 1) ? ypart32 : nullptr));
         HIPCHK(launch_colsum(d, 0, st));
         HIPCHK(launch_dots<double>(d, ypart, ysplit, 1, qcur, qprv, 1, st));
         HIPCHK(launch_colsum(d, 1, st));
@@ -931,7 +938,9 @@ struct Run {
                                    s, nullptr, nullptr, &d.st->done, st));
             return CIQ_OK;
         }
-        HIPCHK(launch_mvm(dtype, mvm_args(operand(j), ypart), st));
+        MvmArgs a = mvm_args(operand(j), ypart);
+        if (part32 && nsplit > 1) a.y32 = ypart32;
+        HIPCHK(launch_mvm(dtype, a, st));
         return CIQ_OK;
     }
 
@@ -1328,6 +1337,12 @@ int solve(int nprob, const ciq_problem* probs, const ciq_opts* o, const void* co
     // the inverse root amplifies the products' FP32 rounding in the
     // noise-level eigendirections; the square root's final K damps it
     main.fine_acc = (mode != CIQ_SQRT) ? 1 : 0;
+    // likewise the square root's resident FP32 / split-FP16 products leave
+    // their column-range partials in FP32 (one rounding each, below that of
+    // the FP32 chunk sums inside them), halving what the reduction reads;
+    // the inverse root keeps FP64 partials
+    main.part32 = (mode == CIQ_SQRT) && nprob == 1 && main.cached && (dtype == CIQ_F32 || dtype == CIQ_F16X3) &&
+                  !precond && post_spec == nullptr && sparse == nullptr && dense == nullptr;
     main.plan(2);
 
     Run<T> bnd;

@@ -58,11 +58,15 @@ hipError_t launch_mvm(int dtype, const MvmArgs& a, hipStream_t st) {
     // Accumulators hold at most 8 (FP32) / 4 (FP64, split forms) column blocks
     // of 16; wider right-hand sides run as column groups, each regenerating its
     // entries.
+    // FP32 partials: the resident FP32 and split-FP16 products only
+    if (a.y32 != nullptr && !((dtype == CIQ_F32 || dtype == CIQ_F16X3) && a.kt != nullptr && a.wl == nullptr))
+        return hipErrorInvalidValue;
     const int cap = product_cap(dtype, a.kt != nullptr);
     for (int c0 = 0; c0 < a.s; c0 += cap) {
         MvmArgs g = a;
         g.s = (a.s - c0 < cap) ? a.s - c0 : cap;
         g.y = static_cast<double*>(a.y) + c0;
+        if (a.y32) g.y32 = a.y32 + c0;
         const int nsb = (g.s + 15) / 16;
         hipError_t e;
         if (dtype == CIQ_F16X3 && a.kt != nullptr) {
@@ -220,7 +224,8 @@ __device__ void scalar_stage(const Dev& d, int tid, int nt, int* active_cnt, int
 
 template <typename T>
 __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit, int nsplit,
-                                                   const T* q, const T* qp, int phase) {
+                                                   const T* q, const T* qp, int phase,
+                                                   const float* __restrict__ y32) {
     __shared__ double sh[256];
     __shared__ double lsum[16 * 64];
     if (d.st->done) return;
@@ -260,7 +265,9 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit
                     const long long idx = (long long)(off + i) * s + c;
 #pragma unroll
                     for (int k = 0; k < MS; ++k)
-                        part[u][k] = (i < n && k < nsplit) ? (double)y[k * ysplit + idx] : 0.0;
+                        part[u][k] = (i < n && k < nsplit)
+                                         ? (y32 ? (double)y32[k * ysplit + idx] : (double)y[k * ysplit + idx])
+                                         : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -286,7 +293,7 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit
                 const int i = i0 + u * G;
                 if (i >= n) break;
                 const long long idx = (long long)(off + i) * s + c;
-                if (nsplit > 1) y[idx] = (T)yv[u];    // the reduced product for phase 1 / update
+                if (nsplit > 1 || y32) y[idx] = (T)yv[u];   // the reduced product for phase 1 / update
                 if (q == nullptr) {                   // ||b||^2
                     acc = fma(yv[u], yv[u], acc);
                     continue;
@@ -308,6 +315,131 @@ __global__ __launch_bounds__(256) void dots_kernel(Dev d, T* y, long long ysplit
         double sum = 0.0;
         for (int r = 0; r < RL; ++r) sum += sh[r * TS + threadIdx.x];
         d.dots[(((long long)p * d.dots_blocks + blockIdx.x) * s + c) * 2 + (q == nullptr ? 1 : phase)] = sum;
+    }
+}
+
+// The same two passes for s in {4, 8, 16, 32, 64} with 16-byte loads: lane
+// (cg, rl) owns columns 4 cg .. 4 cg + 3 of rows rl, rl + RL, ... (RL = 1024 / s
+// rows per block pass), so one load instruction moves 1 KB per wave instead of
+// 256 or 512 bytes (the passes are bound by the bytes in flight). Per element
+// the arithmetic and the order over the split partials are those of
+// dots_kernel; the block partials sum the rows in another order.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+    const dvec2 a = *reinterpret_cast<const dvec2*>(p);
+    const dvec2 b = *reinterpret_cast<const dvec2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load4_nt(const double* p, double (&v)[4]) {
+    const dvec2 a = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+    const dvec2 b = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p + 2));
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load4_nt(const float* p, float (&v)[4]) {
+    const fvec4 a = __builtin_nontemporal_load(reinterpret_cast<const fvec4*>(p));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+// PT: element type of the split partials (phase 0); U: rows per trip
+template <typename PT, int U, int phase>
+__global__ __launch_bounds__(256) void dots_vec_kernel(Dev d, double* y, const PT* yp, long long ysplit,
+                                                       int nsplit, const double* q, const double* qp) {
+    __shared__ double sh[256 * 4];
+    __shared__ double lsum[16 * 64];
+    if (d.st->done) return;
+    const int s = d.s, CG = s >> 2, RL = 256 / CG;
+    const int p = blockIdx.z;
+    const int n = d.n[p], off = d.row_off[p];
+    const int cg = threadIdx.x % CG, rl = threadIdx.x / CG;
+    const int c = 4 * cg, g = p * s + c;
+    double al[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (phase == 1) {
+        if (d.fuse_sums & 2) {   // alpha_j from the phase-0 partials, colsum_lane's fixed order
+            for (int e = threadIdx.x; e < 16 * s; e += 256) {
+                const int r = e / s, col = e - r * s;
+                lsum[r * 64 + col] = colsum_lane(d, 0, p * s + col, r);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                for (int r = 0; r < 16; ++r) al[k] += lsum[r * 64 + c + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) al[k] = d.colsum[g + k];
+        }
+    }
+    double bj[4], acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bj[k] = d.beta_cur[g + k];
+    const int G = gridDim.x * RL;
+    for (int i0 = blockIdx.x * RL + rl; i0 < n; i0 += U * G) {
+        double yv[U][4];
+        if constexpr (phase == 0) {
+            PT part[U][16][4];   // all of a trip's partials requested before they are added
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * G;
+                const long long idx = (long long)(off + i) * s + c;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if (i < n && k < nsplit) {
+                        load4_nt(yp + k * ysplit + idx, part[u][k]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) part[u][k][e] = (PT)0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    yv[u][e] = (double)part[u][0][e];
+#pragma unroll
+                    for (int k = 1; k < 16; ++k)
+                        if (k < nsplit) yv[u][e] += (double)part[u][k][e];
+                }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * G;
+                if (i < n) load4(y + (long long)(off + i) * s + c, yv[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * G;
+            if (i >= n) break;
+            const long long idx = (long long)(off + i) * s + c;
+            if (phase == 0 && (nsplit > 1 || sizeof(PT) == 4)) {   // the reduced product for phase 1 / update
+                *reinterpret_cast<dvec2*>(y + idx) = dvec2{yv[u][0], yv[u][1]};
+                *reinterpret_cast<dvec2*>(y + idx + 2) = dvec2{yv[u][2], yv[u][3]};
+            }
+            double qv[4], qpv[4];
+            load4(q + idx, qv);
+            load4(qp + idx, qpv);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double vT = yv[u][e] - bj[e] * qpv[e];
+                if (phase == 0) {
+                    acc[e] = fma(qv[e], vT, acc[e]);
+                } else {
+                    const double v = vT - al[e] * qv[e];
+                    acc[e] = fma(v, v, acc[e]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh[threadIdx.x * 4 + e] = acc[e];
+    __syncthreads();
+    if (threadIdx.x < s) {
+        const int col = threadIdx.x, cgc = col >> 2, e = col & 3;
+        double sum = 0.0;
+        for (int r = 0; r < RL; ++r) sum += sh[(r * CG + cgc) * 4 + e];
+        d.dots[(((long long)p * d.dots_blocks + blockIdx.x) * s + col) * 2 + phase] = sum;
     }
 }
 
@@ -348,13 +480,32 @@ hipError_t launch_colsum(const Dev& d, int k, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_dots(const Dev& d, T* y, long long ysplit, int nsplit, const T* q, const T* qp,
-                       int phase, hipStream_t st) {
+                       int phase, hipStream_t st, const float* y32) {
+    if (y32 != nullptr && (phase != 0 || nsplit > 16)) return hipErrorInvalidValue;
+    const bool vec_s = d.s == 4 || d.s == 8 || d.s == 16 || d.s == 32 || d.s == 64;
+    if (sizeof(T) == 8 && q != nullptr && qp != nullptr && vec_s && nsplit <= 16 && (phase == 0 || nsplit == 1)) {
+        dim3 grid(d.dots_blocks, 1, d.nprob);
+        double* yd = reinterpret_cast<double*>(y);
+        const double* qd = reinterpret_cast<const double*>(q);
+        const double* qpd = reinterpret_cast<const double*>(qp);
+        if (phase == 1)
+            hipLaunchKernelGGL((dots_vec_kernel<double, 4, 1>), grid, dim3(256), 0, st, d, yd, (const double*)yd,
+                               0LL, 1, qd, qpd);
+        else if (y32 != nullptr)
+            hipLaunchKernelGGL((dots_vec_kernel<float, 1, 0>), grid, dim3(256), 0, st, d, yd, y32, ysplit, nsplit,
+                               qd, qpd);
+        else
+            hipLaunchKernelGGL((dots_vec_kernel<double, 1, 0>), grid, dim3(256), 0, st, d, yd, (const double*)yd,
+                               ysplit, nsplit, qd, qpd);
+        return hipGetLastError();
+    }
     const int TS = col_tile(d.s);
     dim3 grid(d.dots_blocks, (d.s + TS - 1) / TS, d.nprob);
-    hipLaunchKernelGGL(dots_kernel<T>, grid, dim3(256), 0, st, d, y, ysplit, nsplit, q, qp, phase);
+    hipLaunchKernelGGL(dots_kernel<T>, grid, dim3(256), 0, st, d, y, ysplit, nsplit, q, qp, phase, y32);
     return hipGetLastError();
 }
-template hipError_t launch_dots<double>(const Dev&, double*, long long, int, const double*, const double*, int, hipStream_t);
+template hipError_t launch_dots<double>(const Dev&, double*, long long, int, const double*, const double*, int, hipStream_t,
+                                        const float*);
 
 // ----------------------------------------------------------------------------
 // Scalar stage (single block, FP64). Initial form: beta_1 = ||b||.

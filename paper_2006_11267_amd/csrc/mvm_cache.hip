@@ -338,6 +338,7 @@ __device__ __forceinline__ void kt32_item(const MvmArgs& a, int p, int rb, int s
     const double s2 = (p < 0) ? a.s2 : (double)a.ps2[p];
     const float* __restrict__ v = static_cast<const float*>(a.v) + off * a.ldv;
     double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit + off * a.ldy;
+    float* __restrict__ y32 = a.y32 ? a.y32 + (long long)split * a.ysplit + off * a.ldy : nullptr;
     const int s = a.s, ldv = a.ldv, ldy = a.ldy;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -511,7 +512,8 @@ __device__ __forceinline__ void kt32_item(const MvmArgs& a, int p, int rb, int s
                     }
                     double val = o2 * sum;
                     if (split == 0) val = fma(s2, (double)v[(long long)i * ldv + cc], val);
-                    y[(long long)i * ldy + cc] = val;
+                    if (y32) y32[(long long)i * ldy + cc] = (float)val;
+                    else y[(long long)i * ldy + cc] = val;
                 }
             }
         }
@@ -568,6 +570,7 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
     const f16x8* __restrict__ vt = static_cast<const f16x8*>(a.vt);
     const long long kstride = (long long)a.nsbt * 128;          // units per k-step
     double* __restrict__ y = static_cast<double*>(a.y) + (long long)split * a.ysplit;
+    float* __restrict__ y32 = a.y32 ? a.y32 + (long long)split * a.ysplit : nullptr;
     const int s = a.s, ldv = a.ldv, ldy = a.ldy;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -669,7 +672,8 @@ __global__ __launch_bounds__(64 * WAVES) void mvm_kt16_kernel(MvmArgs a) {
                     const double kv = accd[rt][sb][r] + (double)ax[rt][sb][r] * k11;
                     double val = o2 * kv * vi;
                     if (split == 0) val = fma(s2, v[(long long)i * ldv + cc], val);
-                    y[(long long)i * ldy + cc] = val;
+                    if (y32) y32[(long long)i * ldy + cc] = (float)val;
+                    else y[(long long)i * ldy + cc] = val;
                 }
             }
         }
