@@ -736,15 +736,18 @@ struct Run {
 
     void configure(int rt_) {
         rt = rt_;
-        {   // ~8 rows per thread in the inner-product kernels. The scalar
-            // stage sums both inner products' block partials itself; with few
-            // blocks phase 1 sums the alpha partials itself too. The
-            // preconditioned step reads the block-summed alpha (colsum) and
-            // writes beta^2 there itself.
+        {   // ~8 rows per thread in the inner-product kernels, at most 512
+            // blocks: their partials are summed per column by single-block
+            // stages, and at N = 50,000, S = 64 a step with 512 blocks takes
+            // 12-14 us less than with 1024 (256 leave the passes short of
+            // loads in flight; measured). The scalar stage sums both inner
+            // products' block partials itself; with few blocks phase 1 sums
+            // the alpha partials itself too. The preconditioned step reads
+            // the block-summed alpha (colsum) and writes beta^2 there itself.
             int ts = 1;
             while (ts < s && ts < 64) ts <<= 1;
             const int rows_per_pass = 256 / ts;
-            d.dots_blocks = std::min(1024, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
+            d.dots_blocks = std::min(512, std::max(1, (max_n + rows_per_pass * 8 - 1) / (rows_per_pass * 8)));
             d.fuse_sums = precond ? 0 : (d.dots_blocks <= 32 ? 3 : 1);
         }
         const int rpb = rows_per_block();
