@@ -46,7 +46,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # runs of `bench.py --counters [--precision f64|f16x3]`, each scaled by the
 # same counter's reading for a plain 512 MiB device copy
 # (profiles/mvm_kt*_kernel_matern52_n50000_s64_hbm_traffic.md).
-KT_TRAFFIC_BYTES = {"f64": 2.1359e10, "f32": 1.0670e10, "f16x3": 1.0595e10}
+KT_TRAFFIC_BYTES = {"f64": 2.1359e10, "f32": 1.0345e10, "f16x3": 1.0352e10}
 METRIC = "K^{±1/2}B columns/s at rel err ≤1e-4 (N=50k); kernel-MVM MFMA util %"
 HBM_PEAK_GBS = 8000.0
 
