@@ -266,6 +266,44 @@ def test_krylov_basis_matches_direction_recurrence(prec, cache):
         assert err_on <= 1.5 * err_off + 1e-12
 
 
+@pytest.mark.parametrize("s", [4, 8, 32])
+def test_inner_product_passes_all_widths(s):
+    """The 16-byte inner-product passes (four columns per lane) at the widths
+    the workloads above do not use, ragged rows: FP64 at small J against the
+    oracle to rounding (FP64 split partials), and the FP32 resident square
+    root, whose products leave FP32 split partials, converged against the
+    oracle at the FP32 bar."""
+    torch = torch_cuda()
+    ciq = ciq_module()
+    rng = np.random.default_rng(300 + s)
+    n = 4099
+    x = rng.random((n, 3))
+    b = rng.standard_normal((n, s))
+    K = okern.kernel_matrix("rbf", x, [0.3], 1.2, 0.02)
+    lam = np.linalg.eigvalsh(K)
+    bounds = (lam[0], lam[-1])
+    announce(f"inner-product passes s={s} n={n}")
+    prob = ciq.Problem(torch.from_numpy(x).cuda(), "rbf", [0.3], 1.2, 0.02)
+    bt = torch.from_numpy(b).cuda()
+    for mode, fn in [("invsqrt", ciq.ciq_invsqrt_mvm), ("sqrt", ciq.ciq_sqrt_mvm)]:
+        out, info, _ = fn(prob, bt, q=8, max_iter=6, tol=0.0, bounds=bounds, kernel_cache="on")
+        ref, oinfo = ociq.ciq(lambda v: K @ v, b, bounds[0], bounds[1], 8, 6, 0.0, mode)
+        assert info["iters"] == oinfo.iters == 6
+        gap = colwise_rel(out.cpu().numpy(), ref).max()
+        assert gap < 1e-11, (mode, gap)
+    x32, b32 = x.astype(np.float32), b.astype(np.float32)
+    K32 = okern.kernel_matrix("rbf", x32.astype(np.float64), [0.3], 1.2, 0.02)
+    lam32 = np.linalg.eigvalsh(K32)
+    bounds32 = (lam32[0], lam32[-1])
+    prob32 = ciq.Problem(torch.from_numpy(x32).cuda(), "rbf", [0.3], 1.2, 0.02)
+    out, info, _ = ciq.ciq_sqrt_mvm(prob32, torch.from_numpy(b32).cuda(), q=12, max_iter=1000, tol=1e-6,
+                                    bounds=bounds32, kernel_cache="on")
+    ref, _ = ociq.ciq(lambda v: K32 @ v, b32.astype(np.float64), bounds32[0], bounds32[1], 12, 1000, 1e-10, "sqrt")
+    err = colwise_rel(out.cpu().numpy(), ref).max()
+    print(f"s={s}: FP32 resident square root vs oracle {err:.2e} ({info['iters']} iterations)", flush=True)
+    assert info["converged"] and err < 1e-4, err
+
+
 def test_krylov_basis_chunks_reused_across_calls(monkeypatch):
     """The basis slots live in chunks kept between calls. With 2 MiB chunks
     (five slots of n = 2345, s = 19) every run crosses many chunk boundaries
