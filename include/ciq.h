@@ -178,11 +178,13 @@ typedef struct ciq_opts {
                                   run from the logged direction coefficients,
                                   instead of moving Q direction vectors every
                                   iteration (the same result up to rounding).
-                                  The vectors live in 2 GiB chunks that stay
-                                  allocated on the device after the call for
-                                  the next one (ciq_release_workspace returns
-                                  them); a chunk the device cannot supply in the
-                                  middle of a run ends it with CIQ_ENOMEM.
+                                  The vectors live in 2 GiB chunks
+                                  ($CIQ_BASIS_CHUNK_MIB sets another size) that
+                                  stay allocated on the device after the call
+                                  for the next one (ciq_release_workspace
+                                  returns them); a chunk the device cannot
+                                  supply in the middle of a run ends it with
+                                  CIQ_ENOMEM.
                                   CIQ_BASIS_OFF: the direction recurrence.       */
     int32_t reserved;
 } ciq_opts;
