@@ -99,8 +99,10 @@ int basis_pool_release(int dev) {
 }
 
 // hipMalloc on the current device; when the device is short it first returns
-// the basis chunks kept from earlier calls and tries once more.
-bool dev_malloc(void** p, size_t bytes) {
+// the basis chunks kept from earlier calls and tries once more. `locked`: the
+// caller holds the device's scratch lock; otherwise the lock is taken here
+// for the release (a solve running on another thread finishes first).
+bool dev_malloc(void** p, size_t bytes, bool locked = true) {
     if (hipMalloc(p, bytes) == hipSuccess) return true;
     (void)hipGetLastError();
     *p = nullptr;
@@ -109,6 +111,8 @@ bool dev_malloc(void** p, size_t bytes) {
         (void)hipGetLastError();
         return false;
     }
+    std::unique_lock<std::mutex> lk(g_scratch[dev].mu, std::defer_lock);
+    if (!locked) lk.lock();
     if (g_basis[dev].chunks.empty() && !g_basis[dev].logs) return false;
     if (basis_pool_release(dev) != CIQ_OK) return false;
     if (hipMalloc(p, bytes) == hipSuccess) return true;
@@ -2225,7 +2229,7 @@ int ciq_svgp_predict(const ciq_problem* z, const void* x, int nb, const double* 
         }
     };
     layout(nullptr);
-    if (!dev_malloc(&mem.p, off)) {
+    if (!dev_malloc(&mem.p, off, false)) {   // no lock held here: the solves below take it
         (void)hipGetLastError();
         mem.p = nullptr;
         return CIQ_ENOMEM;
@@ -2333,7 +2337,7 @@ int ciq_pivoted_cholesky(const ciq_problem* p, int dtype, int rank, double* l_ou
         pchol_layout(n, rank, [&](size_t c) { return carve<double>(base, off, c); }, w);
     };
     layout(nullptr);
-    if (!dev_malloc(&mem.p, off)) {
+    if (!dev_malloc(&mem.p, off, false)) {
         (void)hipGetLastError();
         mem.p = nullptr;
         return CIQ_ENOMEM;
