@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "ciq.h"
+#include "basis_slots.h"
 #include "ciq_internal.h"
 
 namespace ciq {
@@ -155,8 +156,7 @@ struct BasisSlots {
         slots = std::min(slots, max_slots);
         if (slots <= cap) return CIQ_OK;
         BasisPool& bp = g_basis[dev];
-        const int first = cap;
-        const size_t kend = ((size_t)slots + per_chunk - 1) / per_chunk;   // chunks that cover the slots
+        const size_t kend = basis_chunks_for(slots, per_chunk);   // chunks that cover the slots
         while (bp.chunks.size() < kend) {
             void* p = nullptr;
             if (hipMalloc(&p, bp.chunk_bytes) != hipSuccess) {
@@ -165,15 +165,15 @@ struct BasisSlots {
             }
             bp.chunks.push_back(p);
         }
-        cap = (int)std::min(kend * per_chunk, (size_t)max_slots);
-        for (size_t k0 = (size_t)first / per_chunk; k0 < kend; k0 += kBasisChunksPerLaunch) {
+        hipError_t e = hipSuccess;
+        cap = basis_table_ranges(cap, slots, per_chunk, max_slots, kBasisChunksPerLaunch, [&](int lo, int hi, int k0) {
+            if (e != hipSuccess) return;
             BasisChunks c{};
-            for (int u = 0; u < kBasisChunksPerLaunch && k0 + u < kend; ++u)
-                c.base[u] = static_cast<char*>(bp.chunks[k0 + u]);
-            const int lo = std::max(first, (int)(k0 * per_chunk));
-            const int hi = (int)std::min((k0 + kBasisChunksPerLaunch) * per_chunk, (size_t)cap);
-            HIPCHK(launch_basis_table(tab, lo, hi, per_chunk, stride, (int)k0, c, st));
-        }
+            for (int u = 0; u < kBasisChunksPerLaunch && (size_t)(k0 + u) < bp.chunks.size(); ++u)
+                c.base[u] = static_cast<char*>(bp.chunks[(size_t)k0 + u]);
+            e = launch_basis_table(tab, lo, hi, per_chunk, stride, k0, c, st);
+        });
+        HIPCHK(e);
         return CIQ_OK;
     }
 };
